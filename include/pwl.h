@@ -1,0 +1,204 @@
+/*
+ * pwl.h - C ABI of the MI355X (gfx950) library for evaluating a continuous
+ * function through its near-optimal continuous piecewise-linear (CPWL)
+ * approximation.
+ *
+ * Method: Berjon, Gallego, Cuevas, Moran, Garcia, "Optimal Piecewise Linear
+ * Function Approximation for GPU-based Applications", IEEE Trans. Cybernetics
+ * 2015 (arXiv 1510.02975).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Point arrays (x, y, g, dx, seg) and the value arrays v_override / dv are
+ *    caller-owned DEVICE memory on the current HIP device, contiguous FP32
+ *    (int32 for seg).  16-byte alignment of all point arrays selects the
+ *    vectorised kernels; any other alignment is accepted and served by a
+ *    scalar kernel.
+ *  - Tables (pwl_table) and batches (pwl_batch) are opaque, owned by the
+ *    library and resident in device memory; free them with the matching
+ *    *_free call.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Every call is enqueued on that stream and returns without
+ *    waiting, except pwl_table_check, pwl_table_download and the create
+ *    calls, which synchronise the stream they are given.
+ *  - Arguments are validated on the host before anything is enqueued; an
+ *    invalid call enqueues nothing and returns a negative pwl_status.  HIP
+ *    runtime failures return PWL_EHIP.  pwl_last_error() then returns a
+ *    message (thread-local; valid until the next failing call on the thread).
+ *  - n = 0 points is valid and does nothing.
+ *
+ * Evaluation semantics (Algorithm 1, Sec. IV of the paper, plus the readings
+ * this library fixes where the paper is silent):
+ *  - x is clamped to the table domain [a, b] (constant extension);
+ *  - x = b lies in the last segment with fractional distance 1;
+ *  - a point exactly on an interior knot belongs to the segment on its right;
+ *  - NaN x gives NaN y and NaN dL/dx and contributes nothing to dL/dv.
+ */
+#ifndef PWL_H
+#define PWL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PWL_ABI_VERSION 1
+#define PWL_MAX_N 4096     /* segments per table: the table lives in LDS */
+#define PWL_MAX_PARAMS 6
+
+typedef enum pwl_status {
+    PWL_OK = 0,
+    PWL_EINVAL = -1,     /* invalid argument (nothing was enqueued)          */
+    PWL_ENOMEM = -2,     /* device allocation failed                         */
+    PWL_EHIP = -3,       /* HIP runtime error (message in pwl_last_error)    */
+    PWL_EKNOTS = -4,     /* FP32 knots are not strictly increasing           */
+    PWL_ECAPACITY = -5   /* N above PWL_MAX_N or a size limit of the library */
+} pwl_status;
+
+/* The approximated functions f (the paper's normalisation constants are
+ * folded into amp).  params may be NULL/short; missing ones take the
+ * defaults in brackets. */
+typedef enum pwl_func {
+    PWL_F_GAUSSIAN = 0,    /* amp * exp(-x^2 / (2 s^2));  params {s [1], amp [1]}, s > 0   (Sec. VI-A) */
+    PWL_F_LORENTZIAN = 1,  /* amp / (1 + (x / g)^2);      params {g [1], amp [1]}, g > 0   (Sec. VI-B) */
+    PWL_F_BESSEL_J0 = 2,   /* amp * J0(x);                params {amp [1]}                 (Sec. VI-C) */
+    PWL_F_POLY = 16,       /* c0 + c1 x + ... + c5 x^5;   params {c0 .. c5} (test function)           */
+    PWL_F_EXP = 17         /* amp * exp(alpha x);         params {alpha [1], amp [1]} (test function)  */
+} pwl_func;
+
+typedef enum pwl_partition {
+    PWL_UNIFORM = 0,   /* x_k = a + (b - a) k / N (Sec. IV, uniform case)                      */
+    PWL_OPTIMAL = 1    /* quasi-optimal partition F(x_i) = i / N, density |f''|^(2/5) (Sec. III-B1) */
+} pwl_partition;
+
+typedef enum pwl_values {
+    PWL_INTERP = 0,    /* linear interpolant: v_k = f(x_k) (Sec. II-B1)                 */
+    PWL_PROJ = 1       /* L2 orthogonal projection: M c = b, hat basis (Sec. II-B2)     */
+} pwl_values;
+
+/* Flags reported by pwl_table_check. */
+#define PWL_FLAG_DEGENERATE 1       /* f'' == 0 everywhere: optimal partition fell back to uniform */
+#define PWL_FLAG_KNOTS_COLLAPSED 2  /* FP32 knots not strictly increasing: table unusable (NaN)    */
+#define PWL_FLAG_NONFINITE 4        /* the density integral was not finite: uniform fallback       */
+
+typedef struct pwl_table pwl_table;
+typedef struct pwl_batch pwl_batch;
+
+/* ---- tables ----------------------------------------------------------- */
+
+/*
+ * pwl_build - allocate a table and enqueue its construction on `stream`.
+ *   func, params[nparams]  the function f (see pwl_func); nparams in [0, 6].
+ *   a < b                  the domain; both are rounded to FP32 first and the
+ *                          rounded values are the table's domain.
+ *   N                      number of segments, 1 <= N <= PWL_MAX_N.
+ *   partition              PWL_UNIFORM, or PWL_OPTIMAL: the knots x_i solve
+ *                          F(x_i) = i/N where F is the normalised cumulative
+ *                          integral of |f''|^(2/5) (Sec. III-B1, the
+ *                          equations for the local knot density, the
+ *                          partition and F).  F is discretised on M = 256 N
+ *                          cells with the trapezoid rule and an FP64 prefix
+ *                          scan, inverted linearly inside the cell that
+ *                          reaches i S_M / N; knots are rounded to FP32.
+ *   values                 PWL_INTERP: v_k = f(x_k); PWL_PROJ: c solves
+ *                          M c = b with m_ij = <phi_i, phi_j>, b_i = <f, phi_i>
+ *                          (Sec. II-B2); b by 16-point Gauss-Legendre per
+ *                          segment, the tridiagonal solve in FP64.
+ *   out                    receives the table (library-owned).
+ * Returns PWL_EINVAL for bad arguments, PWL_ECAPACITY for N > PWL_MAX_N,
+ * PWL_ENOMEM / PWL_EHIP on device failures.  Knot collapse is only known
+ * once the build has run: see pwl_table_check.
+ */
+pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b,
+                     int32_t N, int32_t partition, int32_t values, void* stream, pwl_table** out);
+
+/*
+ * pwl_rebuild - enqueue a new construction into an existing table, reusing
+ * its device memory.  The table keeps its N; every other argument is as in
+ * pwl_build.  The caller must not evaluate the table on another stream
+ * while the rebuild is in flight.
+ */
+pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t nparams, double a,
+                       double b, int32_t partition, int32_t values, void* stream);
+
+/*
+ * pwl_table_check - synchronise `stream` and report the table's build flags
+ * (PWL_FLAG_*) in *flags (nullable).  Returns PWL_EKNOTS if the FP32 knots
+ * collapsed (the table then evaluates to NaN), PWL_OK otherwise.
+ */
+pwl_status pwl_table_check(const pwl_table* t, void* stream, int32_t* flags);
+
+/*
+ * pwl_table_info - host-side description of a table (no device access).
+ * Every output pointer is nullable.  map_cells is the number of cells of the
+ * uniform index map the evaluator uses to locate segments.
+ */
+pwl_status pwl_table_info(const pwl_table* t, int32_t* N, double* a, double* b, int32_t* partition,
+                          int32_t* values, int32_t* map_cells);
+
+/*
+ * pwl_table_download - copy the table to HOST buffers (each nullable):
+ * knots[N+1] FP32 knots, values[N+1] FP32 vertex values, knots64[N+1] FP64
+ * knots before rounding, values64[N+1] FP64 vertex values (for PWL_PROJ the
+ * FP64 solution of M c = b; for PWL_INTERP the FP32 values widened).
+ * Synchronises `stream`.
+ */
+pwl_status pwl_table_download(const pwl_table* t, float* knots, float* values, double* knots64,
+                              double* values64, void* stream);
+
+/* pwl_table_free - release a table (waits for the device to finish with it). NULL is a no-op. */
+void pwl_table_free(pwl_table* t);
+
+/* ---- evaluation (Algorithm 1, Sec. IV) --------------------------------- */
+
+/*
+ * pwl_eval - y[i] = v(x[i]) for i < n.
+ *   v_override  nullable device [N+1] FP32 vertex values used instead of the
+ *               table's own (slopes are then derived from them on the fly).
+ *   x, y        device FP32 [n]; y may not alias x partially (y == x is allowed).
+ */
+pwl_status pwl_eval(const pwl_table* t, const float* v_override, const float* x, float* y, int64_t n,
+                    void* stream);
+
+/*
+ * pwl_eval_backward - fused forward and backward of pwl_eval for an upstream
+ * gradient g: y = v(x) (nullable), dx = g * v'(x) (nullable; 0 where x was
+ * clamped, the left slope at x = b), dv[k] = sum over points of g times the
+ * hat weight phi_k(x) (nullable; device [N+1]; OVERWRITTEN, accumulated with
+ * FP32 atomics, so the summation order is not fixed).  At least one of y, dx,
+ * dv must be non-NULL.
+ */
+pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const float* x,
+                             const float* g, float* y, float* dx, float* dv, int64_t n, void* stream);
+
+/*
+ * pwl_locate - the 0-based segment index i with x_i <= x < x_{i+1} of each
+ * point (step 1 of Algorithm 1), after clamping to [a, b]; x = b gives N-1.
+ * seg is device int32 [n].
+ */
+pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t n, void* stream);
+
+/* ---- baselines and probes ----------------------------------------------- */
+
+/*
+ * pwl_direct_gaussian - y = amp * exp(-x^2 / (2 s^2)) computed directly with
+ * the device math library (fast != 0 selects the reduced-precision
+ * exponential), the comparison the paper makes in Sec. VI-A.
+ */
+pwl_status pwl_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int32_t fast,
+                               void* stream);
+
+/* pwl_copy - dst = src (device FP32 [n]); the HBM bandwidth probe. */
+pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream);
+
+/* ---- library ------------------------------------------------------------ */
+
+const char* pwl_last_error(void);
+int32_t pwl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWL_H */

@@ -1,0 +1,16 @@
+"""MI355X (gfx950) evaluation of continuous functions through their
+near-optimal continuous piecewise-linear approximation (Berjon et al., IEEE
+TCYB 2015, arXiv 1510.02975).
+
+The compute path is the HIP library libpwl.so (C ABI in include/pwl.h);
+`binding` marshals PyTorch tensors and streams into it.  Importing the
+package does not load the library; the first call does, and fails loudly if
+it has not been built.
+"""
+
+from .binding import (  # noqa: F401
+    BESSEL_J0, EXP, FLAG_DEGENERATE, FLAG_KNOTS_COLLAPSED, FLAG_NONFINITE, GAUSSIAN, INTERP,
+    LORENTZIAN, MAX_N, OPTIMAL, POLY, PROJ, UNIFORM, PWLError, PWLFunction, PWLTable, Table,
+    load_library, pwl_abi_version, pwl_build, pwl_copy, pwl_direct_gaussian, pwl_eval,
+    pwl_eval_backward, pwl_last_error, pwl_locate, pwl_rebuild, pwl_table_check,
+    pwl_table_download, pwl_table_free, pwl_table_info)

@@ -1,0 +1,310 @@
+"""Thin ctypes binding over libpwl.so (the C ABI in include/pwl.h).
+
+Each pwl_* function here has the name and argument order of the C entry
+point; it only marshals arguments (tensor data pointers, the current HIP
+stream) and turns a negative status into an exception.  All arithmetic runs
+in the HIP kernels.  PyTorch supplies device memory and streams.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpwl.so")
+
+GAUSSIAN, LORENTZIAN, BESSEL_J0, POLY, EXP = 0, 1, 2, 16, 17
+UNIFORM, OPTIMAL = 0, 1
+INTERP, PROJ = 0, 1
+FLAG_DEGENERATE, FLAG_KNOTS_COLLAPSED, FLAG_NONFINITE = 1, 2, 4
+MAX_N = 4096
+
+STATUS = {0: "PWL_OK", -1: "PWL_EINVAL", -2: "PWL_ENOMEM", -3: "PWL_EHIP", -4: "PWL_EKNOTS",
+          -5: "PWL_ECAPACITY"}
+
+
+class PWLError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+_lib = None
+
+_c_int32 = ctypes.c_int32
+_c_int64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+_SIGNATURES = {
+    "pwl_build": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, _c_int32,
+                             _c_int32, _c_int32, _vp, ctypes.POINTER(_vp)]),
+    "pwl_rebuild": (_c_int32, [_vp, _c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double,
+                               _c_int32, _c_int32, _vp]),
+    "pwl_table_check": (_c_int32, [_vp, _vp, _ip]),
+    "pwl_table_info": (_c_int32, [_vp, _ip, _dp, _dp, _ip, _ip, _ip]),
+    "pwl_table_download": (_c_int32, [_vp, _fp, _fp, _dp, _dp, _vp]),
+    "pwl_table_free": (None, [_vp]),
+    "pwl_eval": (_c_int32, [_vp, _vp, _vp, _vp, _c_int64, _vp]),
+    "pwl_eval_backward": (_c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int64, _vp]),
+    "pwl_locate": (_c_int32, [_vp, _vp, _vp, _c_int64, _vp]),
+    "pwl_direct_gaussian": (_c_int32, [_vp, _vp, _c_int64, ctypes.c_float, ctypes.c_float, _c_int32, _vp]),
+    "pwl_copy": (_c_int32, [_vp, _vp, _c_int64, _vp]),
+    "pwl_last_error": (ctypes.c_char_p, []),
+    "pwl_abi_version": (_c_int32, []),
+}
+
+
+def load_library(path=None):
+    """Load libpwl.so (once).  Raises if the HIP library has not been built:
+    there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError("libpwl.so is not built (expected at %s); run "
+                          "`python -m paper_1510_02975_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        msg = load_library().pwl_last_error()
+        raise PWLError(status, msg.decode() if msg else "")
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t, dtype=torch.float32, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _params(params):
+    params = [] if params is None else [float(p) for p in params]
+    arr = (ctypes.c_double * max(len(params), 1))(*params) if params else None
+    return arr, len(params)
+
+
+class Table:
+    """Owner of a pwl_table handle."""
+
+    def __init__(self, handle, func, params, a, b, N, partition, values):
+        self.handle = handle
+        self.func, self.params = func, tuple(params) if params else ()
+        self.N, self.partition, self.values = N, partition, values
+        self.a, self.b = self.info()[1:3]
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+    def info(self):
+        lib = load_library()
+        N, part, vals, K = _c_int32(), _c_int32(), _c_int32(), _c_int32()
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib.pwl_table_info(self.handle, ctypes.byref(N), ctypes.byref(a), ctypes.byref(b),
+                                  ctypes.byref(part), ctypes.byref(vals), ctypes.byref(K)))
+        return N.value, a.value, b.value, part.value, vals.value, K.value
+
+    def free(self):
+        if self.handle is not None:
+            load_library().pwl_table_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Entry points, same names as the C ABI.
+# ---------------------------------------------------------------------------
+
+def pwl_build(func, params, a, b, N, partition=OPTIMAL, values=PROJ, stream=None, check=True):
+    """Build a table on the current device; returns a Table.  With check the
+    stream is synchronised and a knot collapse raises PWLError."""
+    lib = load_library()
+    arr, npar = _params(params)
+    out = ctypes.c_void_p()
+    _check(lib.pwl_build(int(func), arr, npar, float(a), float(b), int(N), int(partition), int(values),
+                         _stream(stream), ctypes.byref(out)))
+    t = Table(out, func, params, a, b, int(N), partition, values)
+    if check:
+        pwl_table_check(t, stream)
+    return t
+
+
+def pwl_rebuild(table, func, params, a, b, partition=OPTIMAL, values=PROJ, stream=None):
+    lib = load_library()
+    arr, npar = _params(params)
+    _check(lib.pwl_rebuild(table.handle, int(func), arr, npar, float(a), float(b), int(partition),
+                           int(values), _stream(stream)))
+    table.func, table.params, table.partition, table.values = func, tuple(params or ()), partition, values
+
+
+def pwl_table_check(table, stream=None):
+    """Synchronise and return the build flags; raises PWLError on knot collapse."""
+    flags = _c_int32()
+    _check(load_library().pwl_table_check(table.handle, _stream(stream), ctypes.byref(flags)))
+    return flags.value
+
+
+def pwl_table_info(table):
+    return table.info()
+
+
+def pwl_table_download(table, stream=None):
+    """Host copies: dict of numpy arrays knots (f32), values (f32), knots64, values64."""
+    import numpy as np
+    n1 = table.N + 1
+    k32 = np.empty(n1, np.float32)
+    v32 = np.empty(n1, np.float32)
+    k64 = np.empty(n1, np.float64)
+    v64 = np.empty(n1, np.float64)
+    _check(load_library().pwl_table_download(
+        table.handle, k32.ctypes.data_as(_fp), v32.ctypes.data_as(_fp), k64.ctypes.data_as(_dp),
+        v64.ctypes.data_as(_dp), _stream(stream)))
+    return {"knots": k32, "values": v32, "knots64": k64, "values64": v64}
+
+
+def pwl_table_free(table):
+    table.free()
+
+
+def pwl_eval(table, x, y=None, v_override=None, stream=None):
+    if y is None:
+        y = torch.empty_like(x)
+    if y.numel() != x.numel():
+        raise ValueError("y must have as many elements as x")
+    if v_override is not None and v_override.numel() != table.N + 1:
+        raise ValueError("v_override must have N + 1 elements")
+    _check(load_library().pwl_eval(table.handle, _ptr(v_override, name="v_override"), _ptr(x, name="x"),
+                                   _ptr(y, name="y"), x.numel(), _stream(stream)))
+    return y
+
+
+def pwl_eval_backward(table, x, g, y=None, dx=None, dv=None, v_override=None, stream=None,
+                      want=("y", "dx", "dv")):
+    """Fused forward + backward; returns (y, dx, dv) with None for outputs not wanted."""
+    if g.numel() != x.numel():
+        raise ValueError("g must have as many elements as x")
+    if y is None and "y" in want:
+        y = torch.empty_like(x)
+    if dx is None and "dx" in want:
+        dx = torch.empty_like(x)
+    if dv is None and "dv" in want:
+        dv = torch.empty(table.N + 1, dtype=torch.float32, device=x.device)
+    if v_override is not None and v_override.numel() != table.N + 1:
+        raise ValueError("v_override must have N + 1 elements")
+    if dv is not None and dv.numel() != table.N + 1:
+        raise ValueError("dv must have N + 1 elements")
+    _check(load_library().pwl_eval_backward(
+        table.handle, _ptr(v_override, name="v_override"), _ptr(x, name="x"), _ptr(g, name="g"),
+        _ptr(y, name="y"), _ptr(dx, name="dx"), _ptr(dv, name="dv"), x.numel(), _stream(stream)))
+    return y, dx, dv
+
+
+def pwl_locate(table, x, seg=None, stream=None):
+    if seg is None:
+        seg = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    _check(load_library().pwl_locate(table.handle, _ptr(x, name="x"), _ptr(seg, torch.int32, "seg"),
+                                     x.numel(), _stream(stream)))
+    return seg
+
+
+def pwl_direct_gaussian(x, y=None, s=1.0, amp=1.0, fast=False, stream=None):
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load_library().pwl_direct_gaussian(_ptr(x, name="x"), _ptr(y, name="y"), x.numel(), float(s),
+                                              float(amp), int(bool(fast)), _stream(stream)))
+    return y
+
+
+def pwl_copy(src, dst=None, stream=None):
+    if dst is None:
+        dst = torch.empty_like(src)
+    _check(load_library().pwl_copy(_ptr(src, name="src"), _ptr(dst, name="dst"), src.numel(),
+                                   _stream(stream)))
+    return dst
+
+
+def pwl_last_error():
+    m = load_library().pwl_last_error()
+    return m.decode() if m else ""
+
+
+def pwl_abi_version():
+    return load_library().pwl_abi_version()
+
+
+# ---------------------------------------------------------------------------
+# Autograd
+# ---------------------------------------------------------------------------
+
+class PWLFunction(torch.autograd.Function):
+    """y = v(x) for the CPWL table with vertex values `values` (a [N+1] FP32
+    tensor, typically a Parameter); backward gives dL/dx and dL/dvalues from
+    the fused HIP kernel."""
+
+    @staticmethod
+    def forward(ctx, x, values, table):
+        x = x.contiguous()
+        values = values.contiguous()
+        ctx.table = table
+        ctx.save_for_backward(x, values)
+        return pwl_eval(table, x, v_override=values)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, values = ctx.saved_tensors
+        table = ctx.table
+        gy = gy.contiguous()
+        need_x, need_v = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        want = tuple(w for w, need in (("dx", need_x), ("dv", need_v)) if need)
+        if not want:
+            return None, None, None
+        _, dx, dv = pwl_eval_backward(table, x, gy, v_override=values, want=want)
+        return dx, dv, None
+
+
+class PWLTable(torch.nn.Module):
+    """A CPWL approximation of f with trainable vertex values."""
+
+    def __init__(self, func, params, a, b, N, partition=OPTIMAL, values=PROJ, device=None):
+        super().__init__()
+        if device is not None:
+            torch.cuda.set_device(device)
+        self.table = pwl_build(func, params, a, b, N, partition, values)
+        v = torch.from_numpy(pwl_table_download(self.table)["values"]).cuda()
+        self.values = torch.nn.Parameter(v)
+
+    def forward(self, x):
+        return PWLFunction.apply(x, self.values, self.table)

@@ -1,0 +1,408 @@
+// Host runtime behind the C ABI declared in include/pwl.h: argument
+// validation (pure host, before any HIP call), the per-table device arena,
+// launch of the build pipeline and of the evaluation kernels, and error
+// reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "pwl.h"
+#include "pwl_internal.h"
+
+namespace pwl {
+hipError_t configure_build_kernels(int max_lds);
+hipError_t configure_eval_kernels(int max_lds);
+}  // namespace pwl
+
+struct pwl_table {
+  int device;
+  int kcap;   // map cells the arena can hold
+  pwl::BuildParams bp;
+  pwl::TableDev td;
+  void* base;
+  size_t bytes;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+pwl_status fail(pwl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define PWL_HIP(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(PWL_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+  } while (0)
+
+// ---- device properties and one-time kernel configuration -------------------
+
+constexpr int kMaxDevices = 64;
+int g_num_cu[kMaxDevices];
+int g_max_lds[kMaxDevices];
+std::once_flag g_cfg_once[kMaxDevices];
+hipError_t g_cfg_err[kMaxDevices];
+
+pwl_status device_ready(int* dev_out, int* num_cu, int* max_lds = nullptr) {
+  int dev = 0;
+  PWL_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PWL_EHIP, "device ordinal %d out of range", dev);
+  std::call_once(g_cfg_once[dev], [dev]() {
+    int cu = 0, lds = 0;
+    hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e == hipSuccess) e = pwl::configure_build_kernels(lds);
+    if (e == hipSuccess) e = pwl::configure_eval_kernels(lds);
+    g_num_cu[dev] = cu > 0 ? cu : 1;
+    g_max_lds[dev] = lds;
+    g_cfg_err[dev] = e;
+  });
+  if (g_cfg_err[dev] != hipSuccess)
+    return fail(PWL_EHIP, "kernel configuration failed: %s", hipGetErrorString(g_cfg_err[dev]));
+  if (dev_out) *dev_out = dev;
+  if (num_cu) *num_cu = g_num_cu[dev];
+  if (max_lds) *max_lds = g_max_lds[dev];
+  return PWL_OK;
+}
+
+// ---- Gauss-Legendre rule on [0, 1] (Newton on the Legendre recurrence) ------
+
+pwl::GaussRule make_gauss_rule() {
+  const int n = pwl::kGaussPoints;
+  pwl::GaussRule r;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute the derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    const double w = 2.0 / ((1.0 - z * z) * dp * dp);
+    r.t[i] = (float)((1.0 - z) / 2.0);   // map [-1, 1] -> [0, 1]
+    r.w[i] = (float)(w / 2.0);
+  }
+  return r;
+}
+
+const pwl::GaussRule& gauss_rule() {
+  static const pwl::GaussRule r = make_gauss_rule();
+  return r;
+}
+
+// ---- argument resolution ----------------------------------------------------
+
+pwl_status resolve_func(int32_t func, const double* params, int32_t nparams, pwl::FuncDesc* fd) {
+  if (nparams < 0 || nparams > PWL_MAX_PARAMS)
+    return fail(PWL_EINVAL, "nparams must be in [0, %d], got %d", PWL_MAX_PARAMS, nparams);
+  if (nparams > 0 && params == nullptr) return fail(PWL_EINVAL, "params is NULL but nparams = %d", nparams);
+  for (int i = 0; i < nparams; ++i)
+    if (!std::isfinite(params[i])) return fail(PWL_EINVAL, "params[%d] is not finite", i);
+  std::memset(fd, 0, sizeof(*fd));
+  fd->func = func;
+  fd->nparams = nparams;
+  auto get = [&](int i, double def) { return i < nparams ? params[i] : def; };
+  switch (func) {
+    case PWL_F_GAUSSIAN:
+    case PWL_F_LORENTZIAN:
+      if (nparams > 2) return fail(PWL_EINVAL, "this function takes at most 2 parameters");
+      fd->p[0] = get(0, 1.0);
+      fd->p[1] = get(1, 1.0);
+      if (!(fd->p[0] > 0.0)) return fail(PWL_EINVAL, "width parameter must be > 0");
+      break;
+    case PWL_F_BESSEL_J0:
+      if (nparams > 1) return fail(PWL_EINVAL, "J0 takes at most 1 parameter (amp)");
+      fd->p[0] = get(0, 1.0);
+      break;
+    case PWL_F_POLY:
+      for (int i = 0; i < PWL_MAX_PARAMS; ++i) fd->p[i] = get(i, 0.0);
+      break;
+    case PWL_F_EXP:
+      if (nparams > 2) return fail(PWL_EINVAL, "exp takes at most 2 parameters");
+      fd->p[0] = get(0, 1.0);
+      fd->p[1] = get(1, 1.0);
+      break;
+    default:
+      return fail(PWL_EINVAL, "unknown function id %d", func);
+  }
+  for (int i = 0; i < PWL_MAX_PARAMS; ++i) fd->p32[i] = (float)fd->p[i];
+  return PWL_OK;
+}
+
+pwl_status resolve_build(int32_t func, const double* params, int32_t nparams, double a, double b,
+                         int32_t N, int32_t partition, int32_t values, pwl::BuildParams* bp) {
+  if (N < 1) return fail(PWL_EINVAL, "N must be >= 1, got %d", N);
+  if (N > PWL_MAX_N) return fail(PWL_ECAPACITY, "N = %d exceeds PWL_MAX_N = %d", N, PWL_MAX_N);
+  if (partition != PWL_UNIFORM && partition != PWL_OPTIMAL)
+    return fail(PWL_EINVAL, "unknown partition %d", partition);
+  if (values != PWL_INTERP && values != PWL_PROJ) return fail(PWL_EINVAL, "unknown values kind %d", values);
+  if (!std::isfinite(a) || !std::isfinite(b)) return fail(PWL_EINVAL, "a and b must be finite");
+  const float a32 = (float)a, b32 = (float)b;
+  if (!std::isfinite(a32) || !std::isfinite(b32) || !(a32 < b32))
+    return fail(PWL_EINVAL, "need a < b after rounding to FP32 (a=%g, b=%g)", a, b);
+  std::memset(bp, 0, sizeof(*bp));
+  pwl_status st = resolve_func(func, params, nparams, &bp->f);
+  if (st != PWL_OK) return st;
+  bp->a = (double)a32;
+  bp->b = (double)b32;
+  bp->a32 = a32;
+  bp->b32 = b32;
+  bp->N = N;
+  bp->K = pwl::map_cells_for(N, partition);
+  bp->scale32 = (float)((double)bp->K / (bp->b - bp->a));
+  bp->M = pwl::kFineCellsPerSegment * N;
+  bp->G = (bp->M + pwl::kDensityCellsPerBlock - 1) / pwl::kDensityCellsPerBlock;
+  bp->partition = partition;
+  bp->values = values;
+  bp->gl = gauss_rule();
+  if (!std::isfinite(bp->scale32) || !(bp->scale32 > 0.0f))
+    return fail(PWL_EINVAL, "domain too narrow for the index map");
+  return PWL_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves the table's arrays out of one allocation (base may be null to size it).
+size_t layout(pwl::TableDev* td, char* base, int N, int K, int G) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  td->rec = reinterpret_cast<float4*>(take(sizeof(float4) * N));
+  td->knots = reinterpret_cast<float*>(take(sizeof(float) * (N + 1)));
+  td->cells = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * K));
+  td->values = reinterpret_cast<float*>(take(sizeof(float) * (N + 1)));
+  td->knots64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
+  td->values64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
+  td->status = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4));
+  td->totals = reinterpret_cast<double*>(take(sizeof(double) * G));
+  td->quad_l = reinterpret_cast<float*>(take(sizeof(float) * N));
+  td->quad_r = reinterpret_cast<float*>(take(sizeof(float) * N));
+  td->ucell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (N + 1)));
+  return off;
+}
+
+pwl::EvalTable eval_view(const pwl_table* t) {
+  pwl::EvalTable e;
+  e.rec = t->td.rec;
+  e.knots = t->td.knots;
+  e.cells = t->td.cells;
+  e.N = t->bp.N;
+  e.K = t->bp.K;
+  e.a32 = t->bp.a32;
+  e.b32 = t->bp.b32;
+  e.scale32 = t->bp.scale32;
+  return e;
+}
+
+pwl_status check_table(const pwl_table* t, int* num_cu) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  int dev = 0;
+  pwl_status st = device_ready(&dev, num_cu);
+  if (st != PWL_OK) return st;
+  if (dev != t->device)
+    return fail(PWL_EINVAL, "table lives on device %d but device %d is current", t->device, dev);
+  return PWL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pwl_abi_version(void) { return PWL_ABI_VERSION; }
+
+const char* pwl_last_error(void) { return g_err.c_str(); }
+
+pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b, int32_t N,
+                     int32_t partition, int32_t values, void* stream, pwl_table** out) {
+  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
+  *out = nullptr;
+  pwl::BuildParams bp;
+  pwl_status st = resolve_build(func, params, nparams, a, b, N, partition, values, &bp);
+  if (st != PWL_OK) return st;
+  int dev = 0, max_lds = 0;
+  st = device_ready(&dev, nullptr, &max_lds);
+  if (st != PWL_OK) return st;
+  const size_t need = std::max(pwl::finalize_lds_bytes(bp.N),
+                               pwl::eval_lds_bytes(bp.N, pwl::map_cells_for(bp.N, PWL_OPTIMAL), true));
+  if (need > (size_t)max_lds)
+    return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", N, need, max_lds);
+  pwl::TableDev td;
+  const int kcap = std::max(pwl::map_cells_for(bp.N, PWL_UNIFORM), pwl::map_cells_for(bp.N, PWL_OPTIMAL));
+  const size_t bytes = layout(&td, nullptr, bp.N, kcap, bp.G);
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, bytes);
+  if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  layout(&td, static_cast<char*>(base), bp.N, kcap, bp.G);
+  pwl_table* t = new pwl_table{dev, kcap, bp, td, base, bytes};
+  e = pwl::launch_build(t->bp, t->td, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    (void)hipFree(base);
+    delete t;
+    return fail(PWL_EHIP, "build launch failed: %s", hipGetErrorString(e));
+  }
+  *out = t;
+  return PWL_OK;
+}
+
+pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t nparams, double a,
+                       double b, int32_t partition, int32_t values, void* stream) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  pwl::BuildParams bp;
+  pwl_status st = resolve_build(func, params, nparams, a, b, t->bp.N, partition, values, &bp);
+  if (st != PWL_OK) return st;
+  if (bp.K > t->kcap)
+    return fail(PWL_ECAPACITY, "rebuild needs %d map cells but the table holds %d", bp.K, t->kcap);
+  st = check_table(t, nullptr);
+  if (st != PWL_OK) return st;
+  t->bp = bp;
+  PWL_HIP(pwl::launch_build(t->bp, t->td, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_table_check(const pwl_table* t, void* stream, int32_t* flags) {
+  pwl_status st = check_table(t, nullptr);
+  if (st != PWL_OK) return st;
+  uint32_t host = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PWL_HIP(hipMemcpyAsync(&host, t->td.status, sizeof(host), hipMemcpyDeviceToHost, s));
+  PWL_HIP(hipStreamSynchronize(s));
+  if (flags) *flags = (int32_t)host;
+  if (host & PWL_FLAG_KNOTS_COLLAPSED)
+    return fail(PWL_EKNOTS, "FP32 knots are not strictly increasing (N too large for the domain)");
+  return PWL_OK;
+}
+
+pwl_status pwl_table_info(const pwl_table* t, int32_t* N, double* a, double* b, int32_t* partition,
+                          int32_t* values, int32_t* map_cells) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (N) *N = t->bp.N;
+  if (a) *a = t->bp.a;
+  if (b) *b = t->bp.b;
+  if (partition) *partition = t->bp.partition;
+  if (values) *values = t->bp.values;
+  if (map_cells) *map_cells = t->bp.K;
+  return PWL_OK;
+}
+
+pwl_status pwl_table_download(const pwl_table* t, float* knots, float* values, double* knots64,
+                              double* values64, void* stream) {
+  pwl_status st = check_table(t, nullptr);
+  if (st != PWL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n1 = (size_t)t->bp.N + 1;
+  if (knots) PWL_HIP(hipMemcpyAsync(knots, t->td.knots, n1 * sizeof(float), hipMemcpyDeviceToHost, s));
+  if (values) PWL_HIP(hipMemcpyAsync(values, t->td.values, n1 * sizeof(float), hipMemcpyDeviceToHost, s));
+  if (knots64)
+    PWL_HIP(hipMemcpyAsync(knots64, t->td.knots64, n1 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (values64)
+    PWL_HIP(hipMemcpyAsync(values64, t->td.values64, n1 * sizeof(double), hipMemcpyDeviceToHost, s));
+  PWL_HIP(hipStreamSynchronize(s));
+  return PWL_OK;
+}
+
+void pwl_table_free(pwl_table* t) {
+  if (t == nullptr) return;
+  (void)hipFree(t->base);
+  delete t;
+}
+
+pwl_status pwl_eval(const pwl_table* t, const float* v_override, const float* x, float* y, int64_t n,
+                    void* stream) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (n == 0) return PWL_OK;
+  if (x == nullptr || y == nullptr) return fail(PWL_EINVAL, "x and y must be non-NULL");
+  int num_cu = 1;
+  pwl_status st = check_table(t, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_eval(eval_view(t), v_override, x, y, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const float* x, const float* g,
+                             float* y, float* dx, float* dv, int64_t n, void* stream) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (y == nullptr && dx == nullptr && dv == nullptr)
+    return fail(PWL_EINVAL, "at least one of y, dx, dv must be non-NULL");
+  if (n > 0 && (x == nullptr || g == nullptr)) return fail(PWL_EINVAL, "x and g must be non-NULL");
+  int num_cu = 1;
+  if (n == 0 && dv == nullptr) return PWL_OK;
+  pwl_status st = check_table(t, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_eval_backward(eval_view(t), v_override, x, g, y, dx, dv, n, num_cu,
+                                    static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t n, void* stream) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (n == 0) return PWL_OK;
+  if (x == nullptr || seg == nullptr) return fail(PWL_EINVAL, "x and seg must be non-NULL");
+  int num_cu = 1;
+  pwl_status st = check_table(t, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_locate(eval_view(t), x, seg, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int32_t fast,
+                               void* stream) {
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (!(s > 0.0f) || !std::isfinite(s) || !std::isfinite(amp))
+    return fail(PWL_EINVAL, "s must be finite and > 0, amp finite");
+  if (n == 0) return PWL_OK;
+  if (x == nullptr || y == nullptr) return fail(PWL_EINVAL, "x and y must be non-NULL");
+  int num_cu = 1;
+  pwl_status st = device_ready(nullptr, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_direct_gaussian(x, y, n, s, amp, fast, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (n == 0) return PWL_OK;
+  if (src == nullptr || dst == nullptr) return fail(PWL_EINVAL, "src and dst must be non-NULL");
+  int num_cu = 1;
+  pwl_status st = device_ready(nullptr, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_copy(src, dst, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+}  // extern "C"

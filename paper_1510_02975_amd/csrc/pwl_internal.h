@@ -1,0 +1,102 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pwl.h"
+
+namespace pwl {
+
+constexpr int kFineCellsPerSegment = 256;   // M = 256 N density cells
+constexpr int kDensityCellsPerBlock = 1024; // cells scanned by one build workgroup
+constexpr int kBuildThreads = 256;
+constexpr int kGaussPoints = 16;            // Gauss-Legendre nodes per segment for <f, phi_k>
+constexpr int kKnotPad = 4;                 // +inf sentinels after the last interior knot in LDS
+
+// The function f and its parameters, resolved on the host (defaults filled in).
+struct FuncDesc {
+  int32_t func;
+  int32_t nparams;
+  double p[PWL_MAX_PARAMS];   // Gaussian {s, amp}; Lorentzian {g, amp}; J0 {amp}; poly c0..c5; exp {alpha, amp}
+  float p32[PWL_MAX_PARAMS];  // the same, rounded to FP32 (FP32 evaluations)
+};
+
+// Device view of a table's persistent arrays.
+struct TableDev {
+  float4* rec;        // [N]   {x_k, v_k, slope_k, 1/h_k}
+  float* knots;       // [N+1] FP32 knots
+  uint32_t* cells;    // [K]   uniform index map: lo | count << 16
+  float* values;      // [N+1] FP32 vertex values
+  double* knots64;    // [N+1] FP64 knots before rounding
+  double* values64;   // [N+1] FP64 vertex values
+  uint32_t* status;   // build flags (PWL_FLAG_*)
+  // build scratch
+  double* totals;     // [G] per-workgroup density sums
+  float* quad_l;      // [N] integral of f (1 - t) h over segment k   (-> b_k)
+  float* quad_r;      // [N] integral of f t h over segment k         (-> b_{k+1})
+  int32_t* ucell;     // [N+1] map cell of every knot
+};
+
+// Everything an evaluation kernel needs about a table.
+struct EvalTable {
+  const float4* rec;
+  const float* knots;
+  const uint32_t* cells;
+  int32_t N, K;
+  float a32, b32, scale32;   // cell(x) = floor((x - a32) * scale32), clamped to [0, K-1]
+};
+
+// Gauss-Legendre rule on [0, 1].
+struct GaussRule {
+  float t[kGaussPoints];
+  float w[kGaussPoints];
+};
+
+struct BuildParams {
+  FuncDesc f;
+  double a, b;       // FP32-rounded domain, promoted
+  float a32, b32, scale32;
+  int32_t N, K, M, G;
+  int32_t partition, values;
+  GaussRule gl;
+};
+
+// LDS bytes of the evaluation kernels for a table of N segments and K cells.
+inline size_t eval_lds_bytes(int N, int K, bool backward) {
+  size_t b = sizeof(float4) * (size_t)N + sizeof(float) * (size_t)(N + kKnotPad) +
+             sizeof(uint32_t) * (size_t)K;
+  if (backward) b += sizeof(float) * (size_t)(N + 1);
+  return b;
+}
+
+inline size_t finalize_lds_bytes(int N) { return 4 * sizeof(double) * (size_t)(N + 1); }
+
+// Number of map cells for a table of N segments (chosen so the backward
+// kernel's LDS stays within the 160 KiB of a gfx950 workgroup).
+inline int map_cells_for(int N, int partition) {
+  if (partition == PWL_UNIFORM) return 2 * N;
+  return (N > 2048) ? 2 * N : 4 * N;
+}
+
+struct LaunchShape {
+  int block;
+  int grid;
+  size_t lds;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s);
+hipError_t launch_eval(const EvalTable& t, const float* v_override, const float* x, float* y,
+                       int64_t n, int num_cu, hipStream_t s);
+hipError_t launch_eval_backward(const EvalTable& t, const float* v_override, const float* x,
+                                const float* g, float* y, float* dx, float* dv, int64_t n, int num_cu,
+                                hipStream_t s);
+hipError_t launch_locate(const EvalTable& t, const float* x, int32_t* seg, int64_t n, int num_cu,
+                         hipStream_t s);
+hipError_t launch_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int fast,
+                                  int num_cu, hipStream_t st);
+hipError_t launch_copy(const float* src, float* dst, int64_t n, int num_cu, hipStream_t s);
+hipError_t configure_kernels();   // raise dynamic-LDS limits once per process
+
+}  // namespace pwl

@@ -1,0 +1,110 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/pwl.h declares, and rejects invalid arguments on the host before any
+device work (no compute call is made here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.gpu_util import ROOT, library
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "pwl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pwl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = header_symbols()
+    for s in ["pwl_build", "pwl_eval", "pwl_eval_backward", "pwl_table_download", "pwl_table_free",
+              "pwl_last_error", "pwl_locate", "pwl_rebuild", "pwl_table_check", "pwl_table_info"]:
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = library()
+    missing = [s for s in header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_abi_version():
+    assert library().pwl_abi_version() == 1
+
+
+def _build(lib, func=0, params=None, n=0, a=-1.0, b=1.0, N=8, part=1, vals=1):
+    out = ctypes.c_void_p(123)
+    arr = (ctypes.c_double * max(1, len(params or [])))(*(params or [])) if params else None
+    st = lib.pwl_build(func, arr, n, a, b, N, part, vals, None, ctypes.byref(out))
+    return st, out
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(N=0), -1),
+    (dict(N=-3), -1),
+    (dict(N=4097), -5),
+    (dict(a=1.0, b=1.0), -1),
+    (dict(a=2.0, b=1.0), -1),
+    (dict(a=float("nan")), -1),
+    (dict(b=float("inf")), -1),
+    (dict(a=1.0, b=1.0 + 1e-9), -1),          # equal after rounding to FP32
+    (dict(func=5), -1),
+    (dict(part=2), -1),
+    (dict(vals=7), -1),
+    (dict(params=[1.0, 2.0, 3.0], n=3), -1),  # Gaussian takes at most 2
+    (dict(params=[-1.0], n=1), -1),           # width must be > 0
+    (dict(params=[float("nan")], n=1), -1),
+    (dict(func=2, params=[1.0, 2.0], n=2), -1),
+    (dict(n=7), -1),
+])
+def test_build_rejects_invalid_arguments_on_host(kw, status):
+    lib = library()
+    st, out = _build(lib, **kw)
+    assert st == status
+    assert out.value is None            # *out cleared, nothing allocated
+    assert len(lib.pwl_last_error()) > 0
+
+
+def test_build_null_out():
+    lib = library()
+    assert lib.pwl_build(0, None, 0, -1.0, 1.0, 8, 1, 1, None, None) == -1
+
+
+def test_calls_on_null_table_are_rejected():
+    lib = library()
+    assert lib.pwl_eval(None, None, None, None, 10, None) == -1
+    assert lib.pwl_eval_backward(None, None, None, None, None, None, None, 10, None) == -1
+    assert lib.pwl_locate(None, None, None, 10, None) == -1
+    assert lib.pwl_table_info(None, None, None, None, None, None, None) == -1
+    assert lib.pwl_table_check(None, None, None) == -1
+    assert lib.pwl_table_download(None, None, None, None, None, None) == -1
+    assert lib.pwl_rebuild(None, 0, None, 0, -1.0, 1.0, 1, 1, None) == -1
+    lib.pwl_table_free(None)   # no-op
+
+
+def test_baseline_argument_checks():
+    lib = library()
+    assert lib.pwl_direct_gaussian(None, None, -1, 1.0, 1.0, 0, None) == -1
+    assert lib.pwl_direct_gaussian(None, None, 4, 0.0, 1.0, 0, None) == -1
+    assert lib.pwl_direct_gaussian(None, None, 4, 1.0, 1.0, 0, None) == -1
+    assert lib.pwl_direct_gaussian(None, None, 0, 1.0, 1.0, 0, None) == 0   # n = 0 does nothing
+    assert lib.pwl_copy(None, None, -2, None) == -1
+    assert lib.pwl_copy(None, None, 0, None) == 0
+    assert lib.pwl_copy(None, None, 5, None) == -1
+
+
+def test_python_binding_names_match_the_abi():
+    import paper_1510_02975_amd as P
+    for s in header_symbols():
+        assert hasattr(P, s), s
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    import paper_1510_02975_amd as P
+    with pytest.raises((ValueError, TypeError)):
+        P.binding._ptr(torch.zeros(4), name="x")
+    with pytest.raises(TypeError):
+        P.binding._ptr(torch.zeros(4, dtype=torch.float64), name="x")

@@ -1,0 +1,131 @@
+"""GPU fused forward + backward against the FP64 oracle gradient and finite
+differences.
+
+dL/dx: |dx - dx_oracle| <= 1e-5 |g slope| pointwise (tier ii).
+dL/dv: |dv_k - dv_oracle_k| <= 1e-5 sum_points |g phi_k(x)| (the FP32 atomics
+reorder the sum, so the bound is normwise per entry).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 512, O.OPTIMAL, O.PROJ),
+    (O.GAUSSIAN, (1.0, 1.0), -4.0, 4.0, 64, O.UNIFORM, O.INTERP),
+    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, O.PROJ),
+    (O.BESSEL_J0, (1.0,), 0.0, 50.0, 1024, O.OPTIMAL, O.INTERP),
+    (O.GAUSSIAN, (1.0, 1.0), -2.0, 2.0, 1, O.UNIFORM, O.PROJ),
+]
+
+
+def _ids(c):
+    return "f%d-N%d-p%d-v%d" % (c[0], c[4], c[5], c[6])
+
+
+def _abs_weight(X, x, g):
+    """sum over points of |g| phi_k(x) for every k (the dv tolerance scale)."""
+    _, _, w = O.evaluate_backward(X, np.zeros(len(X)), x, np.abs(g))
+    return w
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_fused_backward_matches_oracle(case):
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    func, params, a, b, N, part, vals = case
+    say("backward parity %s" % _ids(case))
+    t = P.pwl_build(func, params, a, b, N, part, vals)
+    d = P.pwl_table_download(t)
+    X, v = d["knots"].astype(np.float64), d["values"].astype(np.float64)
+    n = (1 << 20) + 5
+    w = b - a
+    x = W.uniform_points(a - 0.01 * w, b + 0.01 * w, n, 0)
+    x[:N + 1] = d["knots"]           # every knot exactly once, and both ends
+    x[N + 1] = np.nan
+    g = W.upstream_grad(n, 1)
+    xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
+    y, dx, dv = P.pwl_eval_backward(t, xt, gt)
+    y, dx, dv = (u.cpu().numpy().astype(np.float64) for u in (y, dx, dv))
+    x64, g64 = x.astype(np.float64), g.astype(np.float64)
+    yr, dxr, dvr = O.evaluate_backward(X, v, x64, g64)
+    fin = ~np.isnan(x64)
+    assert np.isnan(y[~fin]).all() and np.isnan(dx[~fin]).all()
+    scale = fmax_abs(func, params, a, b)
+    assert np.max(np.abs(y[fin] - yr[fin])) <= Y_TOL * scale
+    i = O.locate(X, x64[fin])
+    slope = (v[i + 1] - v[i]) / (X[i + 1] - X[i])
+    ex = np.abs(dx[fin] - dxr[fin])
+    assert np.all(ex <= GRAD_TOL * np.abs(g64[fin] * slope) + 1e-30)
+    wk = _abs_weight(X, x64[fin], g64[fin])
+    ev = np.abs(dv - dvr)
+    say("  max dv err / scale %.3e" % np.max(ev / np.maximum(wk, 1e-30)))
+    assert np.all(ev <= GRAD_TOL * wk + 1e-30)
+    # partition of unity: sum_k dv_k = sum of g over non-NaN points
+    assert abs(dv.sum() - g64[fin].sum()) <= 1e-5 * np.abs(g64).sum()
+    t.free()
+
+
+def test_backward_output_subsets_agree():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    t = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 300, O.OPTIMAL, O.INTERP)
+    x = torch.from_numpy(W.normal_points(50001, 1.0, 2)).to(dev)
+    g = torch.from_numpy(W.upstream_grad(50001, 3)).to(dev)
+    y, dx, dv = P.pwl_eval_backward(t, x, g)
+    for want in (("y",), ("dx",), ("dv",), ("y", "dx"), ("y", "dv"), ("dx", "dv")):
+        y2, dx2, dv2 = P.pwl_eval_backward(t, x, g, want=want)
+        if "y" in want:
+            assert torch.equal(y2, y)
+        if "dx" in want:
+            assert torch.equal(dx2, dx)
+        if "dv" in want:
+            assert torch.allclose(dv2, dv, rtol=1e-5, atol=1e-4)
+    # forward of the fused kernel equals pwl_eval
+    assert torch.equal(P.pwl_eval(t, x), y)
+    # misaligned (scalar path)
+    y3, dx3, dv3 = P.pwl_eval_backward(t, x[1:], g[1:])
+    assert torch.equal(y3, y[1:]) and torch.equal(dx3, dx[1:])
+    t.free()
+
+
+def test_autograd_function_against_oracle_and_finite_differences():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    m = P.PWLTable(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 512, O.OPTIMAL, O.PROJ)
+    d = P.pwl_table_download(m.table)
+    X = d["knots"].astype(np.float64)
+    xn = W.normal_points(20001, 1.0, 4)
+    x = torch.from_numpy(xn).to(dev).requires_grad_(True)
+    gn = W.upstream_grad(20001, 5)
+    y = m(x)
+    y.backward(torch.from_numpy(gn).to(dev))
+    v = m.values.detach().cpu().numpy().astype(np.float64)
+    _, dxr, dvr = O.evaluate_backward(X, v, xn.astype(np.float64), gn.astype(np.float64))
+    wk = _abs_weight(X, xn.astype(np.float64), gn.astype(np.float64))
+    assert np.all(np.abs(m.values.grad.cpu().numpy() - dvr) <= GRAD_TOL * wk + 1e-30)
+    i = O.locate(X, xn.astype(np.float64))
+    slope = (v[i + 1] - v[i]) / (X[i + 1] - X[i])
+    assert np.all(np.abs(x.grad.cpu().numpy() - dxr) <= GRAD_TOL * np.abs(gn * slope) + 1e-30)
+    # FP64 central differences in x away from knots
+    eps = 1e-6
+    xs = xn.astype(np.float64)
+    gap = np.min(np.abs(xs[:, None] - X[None, :]), axis=1)
+    ok = gap > 4 * eps
+    fd = (O.evaluate(X, v, xs + eps) - O.evaluate(X, v, xs - eps)) / (2 * eps) * gn
+    assert np.max(np.abs(x.grad.cpu().numpy()[ok] - fd[ok])) <= 1e-4 * np.max(np.abs(fd))
+    # y is linear in v: dL/dv from finite differences is exact
+    k = 256
+    e = np.zeros_like(v)
+    e[k] = 1.0
+    fdv = np.sum(gn * (O.evaluate(X, v + e, xs) - O.evaluate(X, v, xs)))
+    assert abs(m.values.grad[k].item() - fdv) <= GRAD_TOL * wk[k]
