@@ -1,0 +1,239 @@
+"""Benchmark of the CPWL evaluation path on one MI355X.
+
+Workload (the headline one): f(x) = exp(-x^2/2) on [-5, 5], quasi-optimal
+partition with N = 1024 segments, L2-projection vertex values; 2^28 FP32
+points x = clip(1.5 Z, -5, 5), seed 0, resident in HBM.  One step is one pass
+of the whole path: the table is rebuilt in place on the GPU (density scan,
+knot inversion, index map, quadrature, FP64 tridiagonal solve, packing) and
+then all 2^28 points are evaluated.  Input/output buffers rotate over three
+sets so no step reads the previous step's cache residue.
+
+Prints one JSON line.  Secondary figures (fused forward+backward on the
+gradient workload, direct expf, copy bandwidth) ride along in "extra".
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoints/s fwd and fwd+bwd, % HBM roofline, max err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+FWD_BYTES_PER_POINT = 8      # x in, y out (FP32)
+FUSED_BYTES_PER_POINT = 16   # x, g in; y, dx out
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_eval_fwd_gauss_n1024.json")
+KERNEL_SOURCES = ["paper_1510_02975_amd/csrc/pwl_eval.hip", "paper_1510_02975_amd/csrc/pwl_locate.h",
+                  "paper_1510_02975_amd/csrc/pwl_internal.h"]
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the forward kernel from the committed counter
+    summary, or None if absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def event_pairs(torch, k):
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+
+
+def timed_median(torch, fn, reps=20, warm=3):
+    for _ in range(warm):
+        fn(0)
+    ev = event_pairs(torch, reps)
+    for i, (s, e) in enumerate(ev):
+        s.record()
+        fn(i)
+        e.record()
+    torch.cuda.synchronize()
+    return float(np.median([s.elapsed_time(e) for s, e in ev])) * 1e-3
+
+
+def cpu_baseline_leg(spec, x_sample, y_gpu_sample, seconds):
+    """The FP64 oracle (test infrastructure, untuned) on a bounded sample of
+    the same workload: one pass = oracle table build + evaluation of the
+    sample, repeated for about `seconds`.  Also returns the GPU output's max
+    error against the oracle on that sample."""
+    import oracle as O
+    x64 = x_sample.astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        tb = O.build_table(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"],
+                           spec["partition"], spec["values"])
+        y_ref = O.evaluate(tb["X"], tb["v"], x64)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    gpts = reps * len(x_sample) / el / 1e9
+    fmax = float(np.max(np.abs(O.f_value(spec["func"], spec["params"], np.linspace(spec["a"], spec["b"], 100001)))))
+    err = float(np.max(np.abs(y_gpu_sample.astype(np.float64) - y_ref))) / fmax
+    return {"value": gpts, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d points of the workload, table build + evaluation, %d passes in %.1f s"
+                      % (len(x_sample), reps, el)}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-sample-log2", type=int, default=23)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    import paper_1510_02975_amd as P
+    from paper_1510_02975_amd import build as B
+    if not os.path.exists(P.binding.LIB_PATH):
+        B.build()
+    P.load_library()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    spec = dict(W.GAUSS_BIG)
+    n = 1 << args.log2n
+    log("generating %d points" % n)
+    x_host = W.gauss_big_points(n)
+    sets = 3
+    xs = [torch.from_numpy(x_host).to(dev) for _ in range(sets)]
+    ys = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(sets)]
+    table = P.pwl_build(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"],
+                        spec["partition"], spec["values"])
+
+    def rebuild():
+        P.pwl_rebuild(table, spec["func"], spec["params"], spec["a"], spec["b"], spec["partition"],
+                      spec["values"])
+
+    log("warmup %d" % args.warmup)
+    for i in range(args.warmup):
+        rebuild()
+        P.pwl_eval(table, xs[i % sets], ys[i % sets])
+    assert P.pwl_table_check(table) == 0
+    torch.cuda.synchronize()
+
+    log("timing %d steps" % args.steps)
+    ev_build = event_pairs(torch, args.steps)
+    ev_eval = event_pairs(torch, args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev_build[i][0].record()
+        rebuild()
+        ev_build[i][1].record()
+        ev_eval[i][0].record()
+        P.pwl_eval(table, xs[i % sets], ys[i % sets])
+        ev_eval[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    eval_s = float(np.mean([s.elapsed_time(e) for s, e in ev_eval])) * 1e-3
+    build_s = float(np.mean([s.elapsed_time(e) for s, e in ev_build])) * 1e-3
+    value = n * args.steps / wall / 1e9
+    achieved = FWD_BYTES_PER_POINT * n / eval_s / 1e9
+    log("step %.3f ms, eval kernel %.1f us (%.0f GB/s), build %.1f us"
+        % (wall / args.steps * 1e3, eval_s * 1e6, achieved, build_s * 1e6))
+    traffic = measured_traffic()
+    m_cpu = min(n, 1 << args.cpu_sample_log2)
+    y_sample = ys[(args.steps - 1) % sets][:m_cpu].cpu().numpy()   # before the extras reuse ys
+
+    extra = {"eval_kernel_us": eval_s * 1e6, "build_us": build_s * 1e6,
+             "eval_only_gpoints_s": n / eval_s / 1e9,
+             "kernel_source_hash": kernel_source_hash()}
+    if not args.no_extra:
+        log("extras: copy, direct expf, fused forward+backward")
+        xa, ya = xs[0], ys[0]
+        t_copy = timed_median(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % sets]))
+        extra["copy_GBs"] = 8.0 * n / t_copy / 1e9
+        for fast in (0, 1):
+            t = timed_median(torch, lambda i: P.pwl_direct_gaussian(xs[i % sets], ys[i % sets], 1.0, 1.0, fast))
+            extra["direct_%s_gpoints_s" % ("fast_expf" if fast else "expf")] = n / t / 1e9
+        gs = dict(W.GRAD)
+        ng = gs["n"]
+        xg_h, gg_h = W.grad_inputs(ng)
+        tg = P.pwl_build(gs["func"], gs["params"], gs["a"], gs["b"], gs["N"], gs["partition"], gs["values"])
+        xg = [torch.from_numpy(xg_h).to(dev) for _ in range(2)]
+        gg = [torch.from_numpy(gg_h).to(dev) for _ in range(2)]
+        yg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
+        dxg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
+        dvg = torch.empty(gs["N"] + 1, dtype=torch.float32, device=dev)
+        t_fb = timed_median(torch, lambda i: P.pwl_eval_backward(tg, xg[i % 2], gg[i % 2], yg[i % 2], dxg[i % 2], dvg))
+        extra["fwd_bwd_workload"] = "gauss_optimal_n512_proj, 2^26 points x~N(0,1), g~N(0,1)"
+        extra["fwd_bwd_gpoints_s"] = ng / t_fb / 1e9
+        extra["fwd_bwd_hbm_frac"] = FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS
+        del xg, gg, yg, dxg
+        tg.free()
+
+    cpu = None
+    max_err = None
+    if not args.no_cpu:
+        log("cpu baseline on %d points" % m_cpu)
+        cpu, max_err = cpu_baseline_leg(spec, x_host[:m_cpu], y_sample, args.cpu_seconds)
+        extra["max_err_rel_maxf_on_cpu_sample"] = max_err
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gauss_optimal_n1024_proj_2^%d" % args.log2n,
+                   "f": "exp(-x^2/2)", "domain": [-5.0, 5.0], "N": 1024, "partition": "optimal",
+                   "values": "L2 projection", "points": n, "x": "clip(1.5 Z, -5, 5), seed 0",
+                   "step": "GPU table rebuild + forward evaluation of all points"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_eval_fwd", "algorithmic_bytes_per_launch": FWD_BYTES_PER_POINT * n},
+        "cpu_baseline": cpu,
+        "max_err": max_err,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    table.free()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

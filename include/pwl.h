@@ -165,9 +165,11 @@ pwl_status pwl_eval(const pwl_table* t, const float* v_override, const float* x,
  * pwl_eval_backward - fused forward and backward of pwl_eval for an upstream
  * gradient g: y = v(x) (nullable), dx = g * v'(x) (nullable; 0 where x was
  * clamped, the left slope at x = b), dv[k] = sum over points of g times the
- * hat weight phi_k(x) (nullable; device [N+1]; OVERWRITTEN, accumulated with
- * FP32 atomics, so the summation order is not fixed).  At least one of y, dx,
- * dv must be non-NULL.
+ * hat weight phi_k(x) (nullable; device [N+1]; OVERWRITTEN: each workgroup
+ * sums its points in FP64 and the workgroup sums are combined with FP32
+ * atomics, so the last bits depend on their order).  At least one of y, dx,
+ * dv must be non-NULL.  This is the exact derivative of Algorithm 1 (the
+ * paper gives none): dy/dx is the segment slope, dy/dv_k the hat weight.
  */
 pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const float* x,
                              const float* g, float* y, float* dx, float* dv, int64_t n, void* stream);
@@ -191,6 +193,24 @@ pwl_status pwl_direct_gaussian(const float* x, float* y, int64_t n, float s, flo
 
 /* pwl_copy - dst = src (device FP32 [n]); the HBM bandwidth probe. */
 pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream);
+
+/* ---- launch tuning -------------------------------------------------------- */
+
+#define PWL_KERNEL_FORWARD 0    /* pwl_eval, pwl_locate   */
+#define PWL_KERNEL_BACKWARD 1   /* pwl_eval_backward      */
+#define PWL_KERNEL_BATCH 2      /* the batched evaluator  */
+
+/*
+ * pwl_set_launch - process-wide launch shape of one evaluation kernel family:
+ * each thread streams `unroll` (1, 2 or 4) 16-byte vectors per iteration,
+ * workgroups have `block` threads (a multiple of 64 in [64, 1024]) and
+ * `wg_per_cu` of them are launched per compute unit (fewer when the table's
+ * LDS footprint does not allow that many).  All three zero restores the
+ * default.  Used by the autotuner; takes effect for later launches.
+ * pwl_get_launch reads the current shape back (outputs nullable).
+ */
+pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t wg_per_cu);
+pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32_t* wg_per_cu);
 
 /* ---- library ------------------------------------------------------------ */
 

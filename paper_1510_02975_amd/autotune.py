@@ -1,0 +1,110 @@
+"""Launch-shape autotuner for the streaming evaluation kernels.
+
+Times every candidate (unroll, block, workgroups per CU) of a kernel family
+on the caller's own table and points with HIP events on the current stream,
+keeps the fastest, and installs it with pwl_set_launch.  Results can be saved
+to and loaded from a JSON file keyed by kernel family.
+
+    python -m paper_1510_02975_amd.autotune --log2n 26
+"""
+
+import argparse
+import itertools
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+DEFAULT_CANDIDATES = {
+    "unroll": (1, 2, 4),
+    "block": (256, 512, 768, 1024),
+    "wg_per_cu": (1, 2, 3, 4),
+}
+
+
+def _time(fn, reps, warm=2):
+    for i in range(warm):
+        fn(i)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for i, (s, e) in enumerate(ev):
+        s.record()
+        fn(i)
+        e.record()
+    torch.cuda.synchronize()
+    return float(np.median([s.elapsed_time(e) for s, e in ev])) * 1e-3
+
+
+def tune(kernel, run, candidates=None, reps=10, verbose=False):
+    """run(i) launches the kernel once on buffer set i; returns (best config,
+    seconds, all results) and installs the best config."""
+    cand = dict(DEFAULT_CANDIDATES)
+    cand.update(candidates or {})
+    results = []
+    for u, blk, w in itertools.product(cand["unroll"], cand["block"], cand["wg_per_cu"]):
+        if blk * w > 2048:
+            continue
+        B.pwl_set_launch(kernel, u, blk, w)
+        t = _time(run, reps)
+        results.append((t, (u, blk, w)))
+        if verbose:
+            print("  kernel %d unroll %d block %4d wg/CU %d: %.1f us" % (kernel, u, blk, w, t * 1e6), flush=True)
+    results.sort()
+    best_t, best = results[0]
+    B.pwl_set_launch(kernel, *best)
+    return best, best_t, results
+
+
+def save(path, configs):
+    with open(path, "w") as fh:
+        json.dump({str(k): list(v) for k, v in configs.items()}, fh, indent=1)
+
+
+def load(path):
+    """Install the configs saved by save(); missing file is a no-op."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        raw = json.load(fh)
+    out = {}
+    for k, v in raw.items():
+        B.pwl_set_launch(int(k), *v)
+        out[int(k)] = tuple(v)
+    return out
+
+
+def main():
+    import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    B.load_library()
+    dev = torch.device("cuda", 0)
+    n = 1 << args.log2n
+    spec = W.GAUSS_BIG
+    t = B.pwl_build(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"], spec["partition"],
+                    spec["values"])
+    xh = W.gauss_big_points(n)
+    xs = [torch.from_numpy(xh).to(dev) for _ in range(3)]
+    ys = [torch.empty(n, device=dev) for _ in range(3)]
+    best_f, tf, _ = tune(B.KERNEL_FORWARD, lambda i: B.pwl_eval(t, xs[i % 3], ys[i % 3]), verbose=True)
+    print("forward best", best_f, "%.1f GB/s" % (8.0 * n / tf / 1e9), flush=True)
+    gs = W.GRAD
+    tg = B.pwl_build(gs["func"], gs["params"], gs["a"], gs["b"], gs["N"], gs["partition"], gs["values"])
+    gh = W.upstream_grad(n)
+    gg = [torch.from_numpy(gh).to(dev) for _ in range(3)]
+    dx = [torch.empty(n, device=dev) for _ in range(3)]
+    dv = torch.empty(gs["N"] + 1, device=dev)
+    best_b, tb, _ = tune(B.KERNEL_BACKWARD,
+                         lambda i: B.pwl_eval_backward(tg, xs[i % 3], gg[i % 3], ys[i % 3], dx[i % 3], dv),
+                         verbose=True)
+    print("backward best", best_b, "%.1f GB/s" % (16.0 * n / tb / 1e9), flush=True)
+    if args.out:
+        save(args.out, {B.KERNEL_FORWARD: best_f, B.KERNEL_BACKWARD: best_b})
+
+
+if __name__ == "__main__":
+    main()

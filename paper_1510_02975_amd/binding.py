@@ -53,6 +53,8 @@ _SIGNATURES = {
     "pwl_locate": (_c_int32, [_vp, _vp, _vp, _c_int64, _vp]),
     "pwl_direct_gaussian": (_c_int32, [_vp, _vp, _c_int64, ctypes.c_float, ctypes.c_float, _c_int32, _vp]),
     "pwl_copy": (_c_int32, [_vp, _vp, _c_int64, _vp]),
+    "pwl_set_launch": (_c_int32, [_c_int32, _c_int32, _c_int32, _c_int32]),
+    "pwl_get_launch": (_c_int32, [_c_int32, _ip, _ip, _ip]),
     "pwl_last_error": (ctypes.c_char_p, []),
     "pwl_abi_version": (_c_int32, []),
 }
@@ -254,6 +256,20 @@ def pwl_copy(src, dst=None, stream=None):
     _check(load_library().pwl_copy(_ptr(src, name="src"), _ptr(dst, name="dst"), src.numel(),
                                    _stream(stream)))
     return dst
+
+
+KERNEL_FORWARD, KERNEL_BACKWARD, KERNEL_BATCH = 0, 1, 2
+
+
+def pwl_set_launch(kernel, unroll=0, block=0, wg_per_cu=0):
+    """Set the launch shape of a kernel family (all zeros: defaults)."""
+    _check(load_library().pwl_set_launch(int(kernel), int(unroll), int(block), int(wg_per_cu)))
+
+
+def pwl_get_launch(kernel):
+    u, b, w = _c_int32(), _c_int32(), _c_int32()
+    _check(load_library().pwl_get_launch(int(kernel), ctypes.byref(u), ctypes.byref(b), ctypes.byref(w)))
+    return u.value, b.value, w.value
 
 
 def pwl_last_error():

@@ -219,6 +219,7 @@ pwl::EvalTable eval_view(const pwl_table* t) {
   e.rec = t->td.rec;
   e.knots = t->td.knots;
   e.cells = t->td.cells;
+  e.meta = t->td.status;
   e.N = t->bp.N;
   e.K = t->bp.K;
   e.a32 = t->bp.a32;
@@ -402,6 +403,22 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
   pwl_status st = device_ready(nullptr, &num_cu);
   if (st != PWL_OK) return st;
   PWL_HIP(pwl::launch_copy(src, dst, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t wg_per_cu) {
+  if (pwl::set_launch(kernel, unroll, block, wg_per_cu) != hipSuccess)
+    return fail(PWL_EINVAL, "invalid launch shape (kernel %d, unroll %d, block %d, wg_per_cu %d)", kernel,
+                unroll, block, wg_per_cu);
+  return PWL_OK;
+}
+
+pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32_t* wg_per_cu) {
+  if (kernel < 0 || kernel > 2) return fail(PWL_EINVAL, "unknown kernel family %d", kernel);
+  const pwl::LaunchConfig c = pwl::get_launch(kernel);
+  if (unroll) *unroll = c.unroll;
+  if (block) *block = c.block;
+  if (wg_per_cu) *wg_per_cu = c.wg_per_cu;
   return PWL_OK;
 }
 

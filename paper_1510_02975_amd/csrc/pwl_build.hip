@@ -226,16 +226,25 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   // 2. uniform index map: lo[u] = #{knots with cell < u}, count = #{cell == u}.
   // Strictly increasing knots have non-decreasing cells; a collapsed table
   // (evaluated as NaN) gets an empty map so no lookup leaves the table.
+  // The largest count (knots sharing one cell) selects the evaluator's
+  // unrolled compare depth.
+  __shared__ int s_maxc;
+  if (tid == 0) s_maxc = 0;
+  __syncthreads();
   const int32_t* uc = td.ucell + 1;   // interior knots 1 .. N-1
+  int my_max = 0;
   for (int u = tid; u < bp.K; u += kFinalizeThreads) {
     uint32_t e = 0u;
     if (!collapsed) {
       const int lo = count_below(uc, N - 1, u, false);
       const int hi = count_below(uc, N - 1, u, true);
-      e = (uint32_t)lo | ((uint32_t)max(hi - lo, 0) << 16);
+      const int cnt = max(hi - lo, 0);
+      e = (uint32_t)lo | ((uint32_t)cnt << 16);
+      my_max = max(my_max, cnt);
     }
     td.cells[u] = e;
   }
+  if (my_max > 0) atomicMax(&s_maxc, my_max);
 
   // 3. vertex values
   if (bp.values == PWL_PROJ) {
@@ -313,9 +322,10 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     td.rec[k] = r;
   }
   if (tid == 0) {
-    uint32_t st = (bp.partition == PWL_UNIFORM) ? 0u : *td.status;
+    uint32_t st = (bp.partition == PWL_UNIFORM) ? 0u : td.status[0];
     if (collapsed) st |= PWL_FLAG_KNOTS_COLLAPSED;
-    *td.status = st;
+    td.status[0] = st;
+    td.status[1] = (uint32_t)s_maxc;
   }
 }
 

@@ -12,7 +12,8 @@ constexpr int kFineCellsPerSegment = 256;   // M = 256 N density cells
 constexpr int kDensityCellsPerBlock = 1024; // cells scanned by one build workgroup
 constexpr int kBuildThreads = 256;
 constexpr int kGaussPoints = 16;            // Gauss-Legendre nodes per segment for <f, phi_k>
-constexpr int kKnotPad = 4;                 // +inf sentinels after the last interior knot in LDS
+constexpr int kKnotPad = 8;                 // NaN sentinels after the last interior knot in LDS
+constexpr int kMaxUnrolledCount = 4;        // knots per map cell handled by unrolled compares
 
 // The function f and its parameters, resolved on the host (defaults filled in).
 struct FuncDesc {
@@ -30,7 +31,7 @@ struct TableDev {
   float* values;      // [N+1] FP32 vertex values
   double* knots64;    // [N+1] FP64 knots before rounding
   double* values64;   // [N+1] FP64 vertex values
-  uint32_t* status;   // build flags (PWL_FLAG_*)
+  uint32_t* status;   // [0] build flags (PWL_FLAG_*), [1] most knots in one map cell
   // build scratch
   double* totals;     // [G] per-workgroup density sums
   float* quad_l;      // [N] integral of f (1 - t) h over segment k   (-> b_k)
@@ -43,6 +44,7 @@ struct EvalTable {
   const float4* rec;
   const float* knots;
   const uint32_t* cells;
+  const uint32_t* meta;      // [0] build flags, [1] most knots sharing one map cell
   int32_t N, K;
   float a32, b32, scale32;   // cell(x) = floor((x - a32) * scale32), clamped to [0, K-1]
 };
@@ -64,26 +66,34 @@ struct BuildParams {
 
 // LDS bytes of the evaluation kernels for a table of N segments and K cells.
 inline size_t eval_lds_bytes(int N, int K, bool backward) {
+  // records, knots (+ sentinels), u16 map lo[0..K] padded to 4 bytes, [FP64 dL/dv]
   size_t b = sizeof(float4) * (size_t)N + sizeof(float) * (size_t)(N + kKnotPad) +
-             sizeof(uint32_t) * (size_t)K;
-  if (backward) b += sizeof(float) * (size_t)(N + 1);
+             sizeof(uint16_t) * (size_t)((K + 2) & ~1);
+  if (backward) b += 8 + sizeof(double) * (size_t)(N + 1);   // 8-byte aligned FP64 dL/dv
   return b;
 }
 
 inline size_t finalize_lds_bytes(int N) { return 4 * sizeof(double) * (size_t)(N + 1); }
 
-// Number of map cells for a table of N segments (chosen so the backward
-// kernel's LDS stays within the 160 KiB of a gfx950 workgroup).
-inline int map_cells_for(int N, int partition) {
-  if (partition == PWL_UNIFORM) return 2 * N;
-  return (N > 2048) ? 2 * N : 4 * N;
-}
+// Number of map cells for a table of N segments: two per segment on a uniform
+// partition (each cell then holds at most one knot), four on the optimal one.
+inline int map_cells_for(int N, int partition) { return (partition == PWL_UNIFORM) ? 2 * N : 4 * N; }
 
 struct LaunchShape {
   int block;
   int grid;
   size_t lds;
 };
+
+// Tunable launch configuration of a streaming kernel family.
+struct LaunchConfig {
+  int unroll;      // float4 vectors per thread per iteration (1, 2 or 4)
+  int block;       // threads per workgroup (multiple of 64, <= 1024)
+  int wg_per_cu;   // workgroups per CU (capped by the table's LDS footprint)
+};
+
+hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu);
+LaunchConfig get_launch(int kernel);
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s);
