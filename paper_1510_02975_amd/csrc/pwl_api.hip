@@ -202,7 +202,7 @@ size_t layout(pwl::TableDev* td, char* base, int N, int K, int G) {
   };
   td->rec = reinterpret_cast<float4*>(take(sizeof(float4) * N));
   td->knots = reinterpret_cast<float*>(take(sizeof(float) * (N + 1)));
-  td->cells = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * K));
+  td->lo = reinterpret_cast<uint16_t*>(take(sizeof(uint16_t) * (K + 1)));
   td->values = reinterpret_cast<float*>(take(sizeof(float) * (N + 1)));
   td->knots64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
   td->values64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
@@ -218,7 +218,7 @@ pwl::EvalTable eval_view(const pwl_table* t) {
   pwl::EvalTable e;
   e.rec = t->td.rec;
   e.knots = t->td.knots;
-  e.cells = t->td.cells;
+  e.lo = t->td.lo;
   e.meta = t->td.status;
   e.N = t->bp.N;
   e.K = t->bp.K;

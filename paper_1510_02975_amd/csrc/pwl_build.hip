@@ -1,12 +1,14 @@
 // Table construction on the GPU.
 //
 //   optimal partition (Sec. III-B1):
-//     k_density_totals   FP64 |f''|^(2/5) on the fine grid, trapezoid sums per workgroup
-//     k_invert_knots     FP64 prefix of those sums, targets i S_M / N, linear inversion
+//     k_density_totals   FP64 |f''|^(2/5) on the fine grid, trapezoid sum per workgroup
+//     k_invert_knots     FP64 prefix of those sums, targets i S_M / N, linear inversion;
+//                        per knot also its map cell and, for the interpolant, f(x_i)
+//   uniform partition (Sec. IV): k_uniform_knots writes the knots, cells and values
+//   projection values (Sec. II-B2):
+//     k_segments         FP32 Gauss-Legendre integrals of f against both hats of every
+//                        segment, one lane per (segment, node)
 //   every table:
-//     k_segments         uniform knots (Sec. IV) if asked; map cell of every knot;
-//                        FP32 vertex values f(x_k) (Sec. II-B1) or FP32 Gauss-Legendre
-//                        integrals of f against both hats of each segment (Sec. II-B2)
 //     k_finalize         one workgroup: the uniform index map, the FP64 solve of
 //                        M c = b (parallel cyclic reduction), knot-collapse check and
 //                        the packed records {x_k, v_k, slope_k, 1/h_k}
@@ -20,13 +22,19 @@ namespace pwl {
 
 namespace {
 
+constexpr int kScanThreads = 1024;      // density workgroup size (one sample per thread)
+constexpr int kScanLanes = 32;          // lanes that sum cells sequentially
+constexpr int kCellsPerScanLane = kDensityCellsPerBlock / kScanLanes;   // 32
+
 // Inclusive trapezoid sums of the density over the cells of workgroup `blk`.
 // Cell j (1-based) spans [t_{j-1}, t_j], t_j = a + j dt, and adds
-// (d_{j-1} + d_j) dt / 2.  Each thread sums its 4 cells sequentially and the
-// thread totals are chained sequentially by thread 0, so the sums are
-// monotone non-decreasing and the block total equals the last sum bit for
-// bit; both kernels below call this same code.  Contraction is off so that
-// every operation is one IEEE-rounded FP64 operation.
+// (d_{j-1} + d_j) dt / 2.  All 1024 threads evaluate the density (one FP64
+// sample each); then 32 lanes each sum 32 consecutive cells sequentially and
+// lane 0 chains the 32 lane totals sequentially.  Every sum therefore
+// extends the previous one by one rounded addition of a non-negative term,
+// so the sums are monotone non-decreasing and the block total equals the
+// last sum bit for bit; both kernels below call this same code.  Contraction
+// is off so that every operation is one IEEE-rounded FP64 operation.
 __device__ double scan_block_cells(const BuildParams& bp, int blk, double* s_d, double* s_tp,
                                    double* s_S) {
 #pragma clang fp contract(off)
@@ -35,79 +43,113 @@ __device__ double scan_block_cells(const BuildParams& bp, int blk, double* s_d, 
   const double dt = (bp.b - bp.a) / (double)bp.M;
   const double hdt = dt / 2.0;
   const int j0 = blk * C;
-  for (int s = tid; s <= C; s += kBuildThreads) {
+  for (int s = tid; s <= C; s += kScanThreads) {
     const int j = j0 + s;
     s_d[s] = (j <= bp.M) ? knot_density(bp.f, bp.a + (double)j * dt) : 0.0;
   }
   __syncthreads();
-  double loc[C / kBuildThreads];
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < C / kBuildThreads; ++q) {
-    const int c = tid * (C / kBuildThreads) + q;
-    const double inc = (j0 + c + 1 <= bp.M) ? (s_d[c] + s_d[c + 1]) * hdt : 0.0;
-    acc = acc + inc;
-    loc[q] = acc;
+  if (tid < kScanLanes) {
+    double acc = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kCellsPerScanLane; ++q) {
+      const int c = tid * kCellsPerScanLane + q;
+      const double inc = (j0 + c + 1 <= bp.M) ? (s_d[c] + s_d[c + 1]) * hdt : 0.0;
+      acc = acc + inc;
+      if (s_S != nullptr) s_S[c] = acc;
+    }
+    s_tp[tid] = acc;
   }
-  s_tp[tid] = acc;
   __syncthreads();
   if (tid == 0) {
     double run = 0.0;
-    for (int t = 0; t < kBuildThreads; ++t) {
+    for (int t = 0; t < kScanLanes; ++t) {
       const double v = s_tp[t];
       s_tp[t] = run;
       run = run + v;
     }
-    s_tp[kBuildThreads] = run;
+    s_tp[kScanLanes] = run;
   }
   __syncthreads();
   if (s_S != nullptr) {
-    const double P = s_tp[tid];
-#pragma unroll
-    for (int q = 0; q < C / kBuildThreads; ++q) s_S[tid * (C / kBuildThreads) + q] = P + loc[q];
+    const int lane = tid / kCellsPerScanLane;   // 1024 threads cover the 1024 cells
+    s_S[tid] = s_tp[lane] + s_S[tid];
   }
-  const double total = s_tp[kBuildThreads];
+  const double total = s_tp[kScanLanes];
   __syncthreads();
   return total;
 }
 
-__global__ __launch_bounds__(kBuildThreads) void k_density_totals(BuildParams bp, TableDev td) {
+__global__ __launch_bounds__(kScanThreads) void k_density_totals(BuildParams bp, TableDev td) {
   __shared__ double s_d[kDensityCellsPerBlock + 1];
-  __shared__ double s_tp[kBuildThreads + 1];
+  __shared__ double s_tp[kScanLanes + 1];
   const double tot = scan_block_cells(bp, blockIdx.x, s_d, s_tp, nullptr);
   if (threadIdx.x == 0) {
     td.totals[blockIdx.x] = tot;
-    if (blockIdx.x == 0) *td.status = 0u;
+    if (blockIdx.x == 0) td.status[0] = 0u;
   }
 }
 
-__device__ void write_uniform_knots(const BuildParams& bp, const TableDev& td, int k) {
+__device__ double uniform_knot(const BuildParams& bp, int k) {
 #pragma clang fp contract(off)
   double x = bp.a + ((bp.b - bp.a) * (double)k) / (double)bp.N;
   if (k == 0) x = bp.a;
   if (k == bp.N) x = bp.b;
-  td.knots64[k] = x;
-  td.knots[k] = (float)x;
+  return x;
 }
 
-__global__ __launch_bounds__(kBuildThreads) void k_invert_knots(BuildParams bp, TableDev td) {
+// Everything a knot needs once its position is known: FP64 and FP32 copies,
+// its map cell (interior knots) and, for the interpolant, f at the FP32 knot.
+__device__ void emit_knot(const BuildParams& bp, const TableDev& td, int k, double x) {
+  const float x32 = (float)x;
+  td.knots64[k] = x;
+  td.knots[k] = x32;
+  if (k >= 1 && k <= bp.N - 1) td.ucell[k] = map_cell(x32, bp.a32, bp.scale32, bp.K);
+  if (bp.values == PWL_INTERP) td.values[k] = f_value32(bp.f, x32);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_invert_knots(BuildParams bp, TableDev td) {
 #pragma clang fp contract(off)
   constexpr int C = kDensityCellsPerBlock;
   __shared__ double s_d[C + 1];
   __shared__ double s_S[C];
-  __shared__ double s_tp[kBuildThreads + 1];
+  __shared__ double s_tp[kScanLanes + 1];
+  __shared__ double s_lane[kScanLanes + 1];
+  __shared__ double s_tot[kMaxDensityBlocks];
   __shared__ double s_off[3];   // offset of this block, offset of the next, S_M
   const int tid = threadIdx.x;
   const int blk = blockIdx.x;
-  if (tid == 0) {
-    double run = 0.0, off = 0.0, next = 0.0;
-    for (int b = 0; b < bp.G; ++b) {
-      if (b == blk) off = run;
-      run = run + td.totals[b];
-      if (b == blk) next = run;
+  for (int b = tid; b < bp.G; b += kScanThreads) s_tot[b] = td.totals[b];
+  __syncthreads();
+  // Prefix of the workgroup totals, chained in two sequential levels (32
+  // lanes of consecutive totals, then the lane sums) so that the offset of
+  // block b + 1 is, bit for bit, the offset of block b plus its total.
+  const int per = (bp.G + kScanLanes - 1) / kScanLanes;
+  const int my_lane = blk / per;
+  if (tid < kScanLanes) {
+    double acc = 0.0, before = 0.0, through = 0.0;
+    for (int q = 0; q < per; ++q) {
+      const int b = tid * per + q;
+      if (b < bp.G) {
+        if (b == blk) before = acc;
+        acc = acc + s_tot[b];
+        if (b == blk) through = acc;
+      }
     }
-    s_off[0] = off;
-    s_off[1] = next;
+    s_lane[tid] = acc;
+    if (tid == my_lane) {
+      s_off[0] = before;
+      s_off[1] = through;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double run = 0.0, base = 0.0;
+    for (int t = 0; t < kScanLanes; ++t) {
+      if (t == my_lane) base = run;
+      run = run + s_lane[t];
+    }
+    s_off[0] = base + s_off[0];
+    s_off[1] = base + s_off[1];
     s_off[2] = run;
   }
   __syncthreads();
@@ -115,15 +157,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_invert_knots(BuildParams bp, 
   if (!(total > 0.0) || !isfinite(total)) {
     // f'' vanishes on the whole grid (or overflowed): uniform fallback.
     if (blk == 0) {
-      for (int k = tid; k <= bp.N; k += kBuildThreads) write_uniform_knots(bp, td, k);
-      if (tid == 0) *td.status = isfinite(total) ? PWL_FLAG_DEGENERATE : PWL_FLAG_NONFINITE;
+      for (int k = tid; k <= bp.N; k += kScanThreads) emit_knot(bp, td, k, uniform_knot(bp, k));
+      if (tid == 0) td.status[0] = isfinite(total) ? PWL_FLAG_DEGENERATE : PWL_FLAG_NONFINITE;
     }
     return;
   }
   scan_block_cells(bp, blk, s_d, s_tp, s_S);
   const double dt = (bp.b - bp.a) / (double)bp.M;
   const double snap = 1e-12 * (bp.b - bp.a);
-  for (int i = 1 + tid; i < bp.N; i += kBuildThreads) {
+  for (int i = 1 + tid; i < bp.N; i += kScanThreads) {
     const double tau = ((double)i * total) / (double)bp.N;
     if (!(off < tau && tau <= next)) continue;
     // smallest c with off + S_local[c] >= tau (exists: the last one equals next)
@@ -138,66 +180,46 @@ __global__ __launch_bounds__(kBuildThreads) void k_invert_knots(BuildParams bp, 
     const double frac = (tau - Sp) / (Sj - Sp);
     double x = (bp.a + (double)(j - 1) * dt) + frac * dt;
     if (fabs(x) <= snap) x = 0.0;
-    td.knots64[i] = x;
-    td.knots[i] = (float)x;
+    emit_knot(bp, td, i, x);
   }
   if (blk == 0 && tid == 0) {
-    td.knots64[0] = bp.a;
-    td.knots[0] = (float)bp.a;
-    td.knots64[bp.N] = bp.b;
-    td.knots[bp.N] = (float)bp.b;
+    emit_knot(bp, td, 0, bp.a);
+    emit_knot(bp, td, bp.N, bp.b);
   }
 }
 
-__global__ __launch_bounds__(kBuildThreads) void k_segments(BuildParams bp, TableDev td) {
+// Uniform partition: knots, cells and interpolant values.
+__global__ __launch_bounds__(kBuildThreads) void k_uniform_knots(BuildParams bp, TableDev td) {
   const int k = blockIdx.x * kBuildThreads + threadIdx.x;
-  if (k > bp.N) return;
-  if (bp.partition == PWL_UNIFORM) {
-    write_uniform_knots(bp, td, k);
+  if (k <= bp.N) emit_knot(bp, td, k, uniform_knot(bp, k));
+  if (k == 0) td.status[0] = 0u;
+}
+
+// <f, phi_k> pieces of every segment by Gauss-Legendre: lane q of a
+// 16-lane group evaluates node q of segment k; the group reduces its
+// (1 - t) f and t f products with cross-lane shuffles.
+__global__ __launch_bounds__(kBuildThreads) void k_segments(BuildParams bp, TableDev td) {
+  const int gid = blockIdx.x * kBuildThreads + threadIdx.x;
+  const int k = gid / kGaussPoints;
+  const int q = gid % kGaussPoints;
+  float sl = 0.0f, sr = 0.0f, h = 0.0f;
+  if (k < bp.N) {
+    const float xk = td.knots[k];
+    h = td.knots[k + 1] - xk;
+    const float t = bp.gl.t[q];
+    const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
+    sl = (1.0f - t) * fq;
+    sr = t * fq;
   }
-  float xk, xk1 = 0.0f;
-  if (bp.partition == PWL_UNIFORM) {
-#pragma clang fp contract(off)
-    double x0 = bp.a + ((bp.b - bp.a) * (double)k) / (double)bp.N;
-    if (k == 0) x0 = bp.a;
-    if (k == bp.N) x0 = bp.b;
-    xk = (float)x0;
-    if (k < bp.N) {
-      double x1 = bp.a + ((bp.b - bp.a) * (double)(k + 1)) / (double)bp.N;
-      if (k + 1 == bp.N) x1 = bp.b;
-      xk1 = (float)x1;
-    }
-  } else {
-    xk = td.knots[k];
-    if (k < bp.N) xk1 = td.knots[k + 1];
-  }
-  if (k >= 1 && k <= bp.N - 1) td.ucell[k] = map_cell(xk, bp.a32, bp.scale32, bp.K);
-  if (bp.values == PWL_INTERP) {
-    td.values[k] = f_value32(bp.f, xk);
-  } else if (k < bp.N) {
-    const float h = xk1 - xk;
-    float sl = 0.0f, sr = 0.0f;
 #pragma unroll
-    for (int q = 0; q < kGaussPoints; ++q) {
-      const float t = bp.gl.t[q];
-      const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
-      sl = fmaf(1.0f - t, fq, sl);
-      sr = fmaf(t, fq, sr);
-    }
+  for (int m = kGaussPoints / 2; m >= 1; m >>= 1) {
+    sl += __shfl_xor(sl, m, kGaussPoints);
+    sr += __shfl_xor(sr, m, kGaussPoints);
+  }
+  if (k < bp.N && q == 0) {
     td.quad_l[k] = h * sl;
     td.quad_r[k] = h * sr;
   }
-}
-
-// Number of entries of the sorted array u[0..n) that are < key (lt) or <= key.
-__device__ int count_below(const int32_t* u, int n, int key, bool inclusive) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    const bool go_right = inclusive ? (u[mid] <= key) : (u[mid] < key);
-    if (go_right) lo = mid + 1; else hi = mid;
-  }
-  return lo;
 }
 
 constexpr int kFinalizeThreads = 1024;
@@ -211,52 +233,66 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   double* B = A + n;
   double* Cu = B + n;
   double* D = Cu + n;
-  __shared__ int s_collapsed;
-  if (tid == 0) s_collapsed = 0;
+  int* s_uc = reinterpret_cast<int*>(D + n);   // map cells of the knots, [N + 1]
+  __shared__ int s_collapsed, s_maxc;
+  if (tid == 0) {
+    s_collapsed = 0;
+    s_maxc = 0;
+  }
   __syncthreads();
 
-  // 1. knot-collapse check on the FP32 knots
+  // 1. knot-collapse check on the FP32 knots; the knots' cells to LDS
   int bad = 0;
   for (int k = tid; k < N; k += kFinalizeThreads)
     if (!(td.knots[k + 1] > td.knots[k])) bad = 1;
   if (bad) atomicOr(&s_collapsed, 1);
+  for (int k = tid; k <= N; k += kFinalizeThreads)
+    s_uc[k] = (k == 0) ? -1 : ((k == N) ? bp.K - 1 : td.ucell[k]);
   __syncthreads();
   const bool collapsed = s_collapsed != 0;
 
-  // 2. uniform index map: lo[u] = #{knots with cell < u}, count = #{cell == u}.
-  // Strictly increasing knots have non-decreasing cells; a collapsed table
-  // (evaluated as NaN) gets an empty map so no lookup leaves the table.
-  // The largest count (knots sharing one cell) selects the evaluator's
-  // unrolled compare depth.
-  __shared__ int s_maxc;
-  if (tid == 0) s_maxc = 0;
-  __syncthreads();
-  const int32_t* uc = td.ucell + 1;   // interior knots 1 .. N-1
+  // 2. uniform index map lo[u] = #{interior knots with cell < u}: segment k
+  // (between knots k and k+1) owns the cells (cell(x_k), cell(x_{k+1})], with
+  // cell(x_0) = -1 and cell(x_N) = K - 1, so every cell is written once.
+  // The longest run of interior knots sharing one cell is the evaluator's
+  // unrolled compare depth.  A collapsed table (evaluated as NaN) gets an
+  // all-zero map so no lookup leaves the table.
   int my_max = 0;
-  for (int u = tid; u < bp.K; u += kFinalizeThreads) {
-    uint32_t e = 0u;
-    if (!collapsed) {
-      const int lo = count_below(uc, N - 1, u, false);
-      const int hi = count_below(uc, N - 1, u, true);
-      const int cnt = max(hi - lo, 0);
-      e = (uint32_t)lo | ((uint32_t)cnt << 16);
-      my_max = max(my_max, cnt);
+  if (!collapsed) {
+    for (int k = tid; k < N; k += kFinalizeThreads) {
+      const int u0 = s_uc[k], u1 = s_uc[k + 1];
+      for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
+      if (k >= 1 && (k == 1 || s_uc[k - 1] != u0)) {   // first interior knot of its cell
+        int run = 1;
+        while (k + run <= N - 1 && s_uc[k + run] == u0) ++run;
+        my_max = max(my_max, run);
+      }
     }
-    td.cells[u] = e;
+  } else {
+    for (int u = tid; u < bp.K; u += kFinalizeThreads) td.lo[u] = 0;
   }
+  if (tid == 0) td.lo[bp.K] = (uint16_t)(N - 1);
   if (my_max > 0) atomicMax(&s_maxc, my_max);
 
   // 3. vertex values
   if (bp.values == PWL_PROJ) {
     // Gram matrix of the hat basis from the element matrix (h/6)[[2,1],[1,2]]
-    // (half hats at both ends), right-hand side b_k = <f, phi_k>.
-    for (int i = tid; i < n; i += kFinalizeThreads) {
+    // (half hats at both ends), right-hand side b_k = <f, phi_k>.  Row i is
+    // owned by thread i mod 1024 for the whole solve: it keeps its diagonal
+    // in registers and publishes the reciprocal for its neighbours.
+    double diag[kRowsPerThread];
+    double* R = B;   // 1 / diagonal, shared
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      const int i = tid + r * kFinalizeThreads;
+      if (i >= n) break;
       const double xi = (double)td.knots[i];
       const double hl = (i > 0) ? xi - (double)td.knots[i - 1] : 0.0;
       const double hr = (i < N) ? (double)td.knots[i + 1] - xi : 0.0;
       A[i] = hl / 6.0;
       Cu[i] = hr / 6.0;
-      B[i] = hl / 3.0 + hr / 3.0;
+      diag[r] = hl / 3.0 + hr / 3.0;
+      R[i] = 1.0 / diag[r];
       D[i] = ((i > 0) ? (double)td.quad_r[i - 1] : 0.0) + ((i < N) ? (double)td.quad_l[i] : 0.0);
     }
     __syncthreads();
@@ -264,37 +300,43 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     // couplings to rows i - s and i + s; after ceil(log2 n) steps the system
     // is diagonal.  No pivoting is needed: M is strictly diagonally dominant.
     for (int s = 1; s < n; s <<= 1) {
-      double na[kRowsPerThread], nb[kRowsPerThread], nc[kRowsPerThread], nd[kRowsPerThread];
+      double na[kRowsPerThread], nc[kRowsPerThread], nd[kRowsPerThread];
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {
         const int i = tid + r * kFinalizeThreads;
         if (i >= n) break;
-        double ai = A[i], bi = B[i], ci = Cu[i], di = D[i];
+        double bi = diag[r], di = D[i];
         double an = 0.0, cn = 0.0;
         if (i - s >= 0) {
-          const double al = -ai / B[i - s];
+          const double al = -A[i] * R[i - s];
           an = al * A[i - s];
           bi += al * Cu[i - s];
           di += al * D[i - s];
         }
         if (i + s < n) {
-          const double ga = -ci / B[i + s];
+          const double ga = -Cu[i] * R[i + s];
           cn = ga * Cu[i + s];
           bi += ga * A[i + s];
           di += ga * D[i + s];
         }
-        na[r] = an; nb[r] = bi; nc[r] = cn; nd[r] = di;
+        na[r] = an; diag[r] = bi; nc[r] = cn; nd[r] = di;
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {
         const int i = tid + r * kFinalizeThreads;
         if (i >= n) break;
-        A[i] = na[r]; B[i] = nb[r]; Cu[i] = nc[r]; D[i] = nd[r];
+        A[i] = na[r]; Cu[i] = nc[r]; D[i] = nd[r];
+        R[i] = 1.0 / diag[r];
       }
       __syncthreads();
     }
-    for (int i = tid; i < n; i += kFinalizeThreads) D[i] = D[i] / B[i];
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      const int i = tid + r * kFinalizeThreads;
+      if (i >= n) break;
+      D[i] = D[i] / diag[r];
+    }
   } else {
     for (int i = tid; i < n; i += kFinalizeThreads) D[i] = (double)td.values[i];
   }
@@ -321,8 +363,9 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     }
     td.rec[k] = r;
   }
+  __syncthreads();
   if (tid == 0) {
-    uint32_t st = (bp.partition == PWL_UNIFORM) ? 0u : td.status[0];
+    uint32_t st = td.status[0];
     if (collapsed) st |= PWL_FLAG_KNOTS_COLLAPSED;
     td.status[0] = st;
     td.status[1] = (uint32_t)s_maxc;
@@ -333,11 +376,16 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
 
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s) {
   if (bp.partition == PWL_OPTIMAL) {
-    hipLaunchKernelGGL(k_density_totals, dim3(bp.G), dim3(kBuildThreads), 0, s, bp, td);
-    hipLaunchKernelGGL(k_invert_knots, dim3(bp.G), dim3(kBuildThreads), 0, s, bp, td);
+    hipLaunchKernelGGL(k_density_totals, dim3(bp.G), dim3(kScanThreads), 0, s, bp, td);
+    hipLaunchKernelGGL(k_invert_knots, dim3(bp.G), dim3(kScanThreads), 0, s, bp, td);
+  } else {
+    const int nb = (bp.N + 1 + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_uniform_knots, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
   }
-  const int nb = (bp.N + 1 + kBuildThreads - 1) / kBuildThreads;
-  hipLaunchKernelGGL(k_segments, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
+  if (bp.values == PWL_PROJ) {
+    const int nb = (bp.N * kGaussPoints + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_segments, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
+  }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), finalize_lds_bytes(bp.N), s, bp, td);
   return hipGetLastError();
 }

@@ -62,8 +62,7 @@ __device__ __forceinline__ void stage_table(const EvalTable& t, const float* __r
   const float qnan = __builtin_nanf("");
   for (int k = tid; k < t.N + kKnotPad; k += nt)
     s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
-  for (int u = tid; u < t.K; u += nt) s.lo[u] = (uint16_t)(t.cells[u] & 0xffffu);
-  if (tid == 0) s.lo[t.K] = (uint16_t)(t.N - 1);
+  for (int u = tid; u <= t.K; u += nt) s.lo[u] = t.lo[u];
 }
 
 __device__ __forceinline__ float clamp_nan(float x, float a, float b) {

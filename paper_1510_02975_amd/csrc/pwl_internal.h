@@ -10,6 +10,7 @@ namespace pwl {
 
 constexpr int kFineCellsPerSegment = 256;   // M = 256 N density cells
 constexpr int kDensityCellsPerBlock = 1024; // cells scanned by one build workgroup
+constexpr int kMaxDensityBlocks = kFineCellsPerSegment * PWL_MAX_N / kDensityCellsPerBlock;
 constexpr int kBuildThreads = 256;
 constexpr int kGaussPoints = 16;            // Gauss-Legendre nodes per segment for <f, phi_k>
 constexpr int kKnotPad = 8;                 // NaN sentinels after the last interior knot in LDS
@@ -27,7 +28,7 @@ struct FuncDesc {
 struct TableDev {
   float4* rec;        // [N]   {x_k, v_k, slope_k, 1/h_k}
   float* knots;       // [N+1] FP32 knots
-  uint32_t* cells;    // [K]   uniform index map: lo | count << 16
+  uint16_t* lo;       // [K+1] uniform index map: lo[u] = #{interior knots in cells < u}
   float* values;      // [N+1] FP32 vertex values
   double* knots64;    // [N+1] FP64 knots before rounding
   double* values64;   // [N+1] FP64 vertex values
@@ -43,7 +44,7 @@ struct TableDev {
 struct EvalTable {
   const float4* rec;
   const float* knots;
-  const uint32_t* cells;
+  const uint16_t* lo;        // [K+1] uniform index map
   const uint32_t* meta;      // [0] build flags, [1] most knots sharing one map cell
   int32_t N, K;
   float a32, b32, scale32;   // cell(x) = floor((x - a32) * scale32), clamped to [0, K-1]
@@ -73,7 +74,10 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
   return b;
 }
 
-inline size_t finalize_lds_bytes(int N) { return 4 * sizeof(double) * (size_t)(N + 1); }
+// PCR rows (4 FP64 diagonals) and the knots' map cells.
+inline size_t finalize_lds_bytes(int N) {
+  return 4 * sizeof(double) * (size_t)(N + 1) + sizeof(int) * (size_t)(N + 1);
+}
 
 // Number of map cells for a table of N segments: two per segment on a uniform
 // partition (each cell then holds at most one knot), four on the optimal one.

@@ -6,11 +6,11 @@
 // FP32 operation below is monotone, so for every knot x_k with
 // cell(x_k) < cell(x) we have x_k <= x, and for every knot with
 // cell(x_k) > cell(x) we have x_k > x.  Storing, per cell u,
-//   lo[u]    = #{interior knots k : cell(x_k) <  u}
-//   count[u] = #{interior knots k : cell(x_k) == u}
-// the segment of x is lo[u] plus the number of the count[u] knots of its
-// cell that are <= x: exact, with no rounding slack, as long as the map is
-// built with this very function.
+//   lo[u] = #{interior knots k : cell(x_k) < u}     (lo[K] = N - 1),
+// cell u holds the count[u] = lo[u+1] - lo[u] knots x_{lo[u]+1} ..., and the
+// segment of x is lo[u] plus the number of those knots that are <= x:
+// exact, with no rounding slack, as long as the map is built with this very
+// function.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,21 +23,6 @@ __device__ __forceinline__ int map_cell(float x, float a32, float scale32, int K
   // fmaxf returns the non-NaN operand, so NaN x lands in cell 0.
   t = fminf(fmaxf(t, 0.0f), (float)(K - 1));
   return (int)t;
-}
-
-// Segment index in [0, N-1] of x (clamped to the domain).  knots[k] holds the
-// interior knot x_k for 1 <= k <= N-1 and +inf for k >= N; cells[u] holds
-// lo | count << 16.
-template <typename KnotPtr, typename CellPtr>
-__device__ __forceinline__ int locate_segment(float x, KnotPtr knots, CellPtr cells, float a32,
-                                              float scale32, int K) {
-  const int u = map_cell(x, a32, scale32, K);
-  const uint32_t e = cells[u];
-  int seg = (int)(e & 0xffffu);
-  const int cnt = (int)(e >> 16);
-  const int lo = seg;
-  for (int j = 1; j <= cnt; ++j) seg += (x >= knots[lo + j]) ? 1 : 0;
-  return seg;
 }
 
 }  // namespace pwl
