@@ -8,8 +8,10 @@ knot inversion, index map, quadrature, FP64 tridiagonal solve, packing) and
 then all 2^28 points are evaluated.  Input/output buffers rotate over three
 sets so no step reads the previous step's cache residue.
 
-Prints one JSON line.  Secondary figures (fused forward+backward on the
-gradient workload, direct expf, copy bandwidth) ride along in "extra".
+Prints one JSON line.  Secondary figures ride along in "extra": the fused
+forward+backward on the gradient workload, direct expf, copy bandwidth, and
+the many-table workload (one batched launch, its graph replay, the fused
+backward, and one launch per table).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 """
@@ -100,7 +102,127 @@ def cpu_baseline_leg(spec, x_sample, y_gpu_sample, seconds):
                       % (len(x_sample), reps, el)}, err
 
 
+def _kernel_rows(csv_path):
+    import csv
+    with open(csv_path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirname, suffix):
+    for root, _, files in os.walk(dirname):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError("no *%s under %s" % (suffix, dirname))
+
+
+def ingest_pmc(fetch_dir, write_dir, command, n_points):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the forward kernel,
+    scaled by the copy kernel's counters over its known 4 n bytes each way;
+    writes the traffic record bench.py reports and a text summary."""
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _kernel_rows(_find(d, "counter_collection.csv"))
+        per = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "k_eval_fwd" if "k_eval_fwd" in name else ("k_copy" if "k_copy" in name else None)
+            if key:
+                per.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)
+        copy_bytes = 4.0 * n_points
+        factor = copy_bytes / float(np.median(per["k_copy"]))
+        out[counter] = {"k_eval_fwd_raw_bytes": float(np.median(per["k_eval_fwd"])),
+                        "k_copy_raw_bytes": float(np.median(per["k_copy"])),
+                        "copy_known_bytes": copy_bytes, "scale": factor,
+                        "k_eval_fwd_bytes": float(np.median(per["k_eval_fwd"])) * factor,
+                        "dispatches": len(per["k_eval_fwd"])}
+    total = out["FETCH_SIZE"]["k_eval_fwd_bytes"] + out["WRITE_SIZE"]["k_eval_fwd_bytes"]
+    rec = {"kernel": "k_eval_fwd", "workload": "gauss_optimal_n1024_proj_2^%d" % int(np.log2(n_points)),
+           "algorithmic_bytes_per_launch": FWD_BYTES_PER_POINT * n_points,
+           "hbm_bytes_per_launch": total, "counters": out,
+           "kernel_source_hash": kernel_source_hash(), "command": command}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def ingest_trace(trace_dir, out_md, command):
+    """Text summary of a rocprofv3 --kernel-trace --stats run."""
+    rows = _kernel_rows(_find(trace_dir, "kernel_stats.csv"))
+    lines = ["# rocprofv3 kernel statistics", "", "Command (from the repository root):", "",
+             "    " + command, "",
+             "| kernel | calls | average us | min us | max us | share |",
+             "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        name = name.split("(")[0] if "(" in name else name
+        lines.append("| %s | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def batch_extra(torch, P, W, dev, args):
+    """Many-table workload: 4096 tables of uneven N and uneven point counts
+    (about 2^28 points in total), one persistent launch (eager and replayed
+    from its captured graph), the fused forward+backward, and the same
+    forward as one pwl_eval launch per table."""
+    log("batch: building 4096 tables")
+    specs = W.many_tables(T=4096, total_points=1 << args.batch_log2n, seed=2)
+    tabs = [P.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"],
+                        check=False) for s in specs]
+    for t in tabs:
+        P.pwl_table_check(t)
+    x_h, offs = W.many_tables_points(specs, seed=0)
+    n = int(offs[-1])
+    log("batch: %d points" % n)
+    x = torch.from_numpy(x_h).to(dev)
+    del x_h
+    y = torch.empty_like(x)
+    bt = P.pwl_batch_create(tabs, offs)
+    t_fwd = timed_median(torch, lambda i: P.pwl_batch_eval(bt, x, y), reps=10)
+    P.pwl_batch_capture(bt, x, y)
+    t_graph = timed_median(torch, lambda i: P.pwl_batch_replay(bt), reps=10)
+    g = torch.from_numpy(W.upstream_grad(n, 1)).to(dev)
+    dx = torch.empty_like(x)
+    dv = torch.empty(bt.dv_len, dtype=torch.float32, device=dev)
+    t_fb = timed_median(torch, lambda i: P.pwl_batch_eval_backward(bt, x, g, y, dx, dv), reps=10)
+    o = [int(v) for v in offs]
+    views = [(t, x[o[k]:o[k + 1]], y[o[k]:o[k + 1]]) for k, t in enumerate(tabs) if o[k + 1] > o[k]]
+
+    def per_table(i):
+        for t, xs, ys in views:
+            P.pwl_eval(t, xs, ys)
+    t_per = timed_median(torch, per_table, reps=3, warm=1)
+    table_bytes = sum(28 * s["N"] for s in specs)
+    bt.free()
+    for t in tabs:
+        t.free()
+    return {"batch_workload": "4096 tables (Gaussian/Lorentzian/J0, N log-uniform 16..4096), %d points" % n,
+            "batch_fwd_gpoints_s": n / t_fwd / 1e9,
+            "batch_fwd_hbm_frac": FWD_BYTES_PER_POINT * n / t_fwd / 1e9 / HBM_PEAK_GBS,
+            "batch_fwd_graph_gpoints_s": n / t_graph / 1e9,
+            "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9,
+            "batch_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * n / t_fb / 1e9 / HBM_PEAK_GBS,
+            "batch_per_table_launches_gpoints_s": n / t_per / 1e9,
+            "batch_grid_fwd": bt.grid_fwd, "batch_runs_fwd": bt.runs_fwd,
+            "batch_table_bytes": table_bytes}
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--ingest-pmc":
+        # --ingest-pmc FETCH_DIR WRITE_DIR LOG2N "command"
+        ingest_pmc(sys.argv[2], sys.argv[3], sys.argv[5], 1 << int(sys.argv[4]))
+        return 0
+    if len(sys.argv) > 1 and sys.argv[1] == "--ingest-trace":
+        # --ingest-trace TRACE_DIR OUT_MD "command"
+        ingest_trace(sys.argv[2], sys.argv[3], sys.argv[4])
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -110,6 +232,8 @@ def main():
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-log2n", type=int, default=28)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,6 +322,8 @@ def main():
         extra["fwd_bwd_hbm_frac"] = FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS
         del xg, gg, yg, dxg
         tg.free()
+        if not args.no_batch:
+            extra.update(batch_extra(torch, P, W, dev, args))
 
     cpu = None
     max_err = None

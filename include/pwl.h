@@ -181,6 +181,55 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
  */
 pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t n, void* stream);
 
+/* ---- batches of tables ------------------------------------------------- */
+
+/*
+ * pwl_batch_create - prepare one launch that evaluates T tables, table t on
+ * the points [offsets[t], offsets[t+1]) of concatenated point arrays.
+ *   tables[T]    tables on the current device; the batch keeps their device
+ *                addresses and shapes, so free (or rebuild) a table only
+ *                after freeing the batches that use it.
+ *   offsets[T+1] HOST array, offsets[0] = 0, non-decreasing (empty tables
+ *                allowed); offsets[T] is the total number of points.
+ * The points are cut into one equal, contiguous chunk per workgroup of a
+ * persistent grid (its size follows the PWL_KERNEL_BATCH launch shape at
+ * creation time); each workgroup walks the table runs of its chunk and
+ * re-stages its LDS copy of the table only when the table changes.
+ * Uploads the plan and synchronises `stream`.
+ */
+pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
+                            pwl_batch** out);
+
+/* pwl_batch_eval - y = v_t(x) for every table t over its points (device FP32 [offsets[T]]). */
+pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream);
+
+/*
+ * pwl_batch_eval_backward - fused forward + backward for every table: y and
+ * dx (each nullable) as in pwl_eval_backward; dv (required) is the
+ * concatenation of every table's N_t + 1 gradients, table t first, and is
+ * OVERWRITTEN.
+ */
+pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g, float* y, float* dx,
+                                   float* dv, void* stream);
+
+/*
+ * pwl_batch_capture - record the launch sequence of pwl_batch_eval (g NULL)
+ * or pwl_batch_eval_backward (g non-NULL) for these exact buffers into a HIP
+ * graph owned by the batch (replacing a previous one); pwl_batch_replay
+ * launches it on `stream`.  The graph uses no memset nodes (dv is cleared by
+ * a kernel).  Capture synchronises `stream`.
+ */
+pwl_status pwl_batch_capture(pwl_batch* bt, const float* x, const float* g, float* y, float* dx, float* dv,
+                             void* stream);
+pwl_status pwl_batch_replay(pwl_batch* bt, void* stream);
+
+/* pwl_batch_info - shape of a batch (outputs nullable): tables, points, dv length, grids, runs. */
+pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int64_t* dv_len, int32_t* grid_fwd,
+                          int32_t* grid_bwd, int32_t* runs_fwd, int32_t* runs_bwd);
+
+/* pwl_batch_free - release a batch and its graph. NULL is a no-op. */
+void pwl_batch_free(pwl_batch* bt);
+
 /* ---- baselines and probes ----------------------------------------------- */
 
 /*

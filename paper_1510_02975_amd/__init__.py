@@ -14,4 +14,5 @@ from .binding import (  # noqa: F401
     KERNEL_BACKWARD, KERNEL_BATCH, KERNEL_FORWARD, load_library, pwl_abi_version, pwl_build, pwl_copy, pwl_direct_gaussian, pwl_eval,
     pwl_eval_backward, pwl_get_launch, pwl_last_error, pwl_locate, pwl_rebuild, pwl_set_launch,
     pwl_table_check,
-    pwl_table_download, pwl_table_free, pwl_table_info)
+    pwl_table_download, pwl_table_free, pwl_table_info, Batch, pwl_batch_capture, pwl_batch_create,
+    pwl_batch_eval, pwl_batch_eval_backward, pwl_batch_free, pwl_batch_info, pwl_batch_replay)

@@ -57,6 +57,29 @@ def tune(kernel, run, candidates=None, reps=10, verbose=False):
     return best, best_t, results
 
 
+def tune_batch(tables, offsets, x, y, candidates=None, reps=5, verbose=False):
+    """Batched kernel: the persistent grid is planned when the batch is
+    created, so every candidate gets its own batch.  Returns (best, s, all)
+    and installs the best shape for PWL_KERNEL_BATCH."""
+    cand = dict(DEFAULT_CANDIDATES)
+    cand.update(candidates or {})
+    results = []
+    for u, blk, w in itertools.product(cand["unroll"], cand["block"], cand["wg_per_cu"]):
+        if blk * w > 2048:
+            continue
+        B.pwl_set_launch(B.KERNEL_BATCH, u, blk, w)
+        bt = B.pwl_batch_create(tables, offsets)
+        t = _time(lambda i: B.pwl_batch_eval(bt, x, y), reps)
+        bt.free()
+        results.append((t, (u, blk, w)))
+        if verbose:
+            print("  batch unroll %d block %4d wg/CU %d: %.1f us" % (u, blk, w, t * 1e6), flush=True)
+    results.sort()
+    best_t, best = results[0]
+    B.pwl_set_launch(B.KERNEL_BATCH, *best)
+    return best, best_t, results
+
+
 def save(path, configs):
     with open(path, "w") as fh:
         json.dump({str(k): list(v) for k, v in configs.items()}, fh, indent=1)
@@ -80,6 +103,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--batch", action="store_true")
     args = ap.parse_args()
     B.load_library()
     dev = torch.device("cuda", 0)
@@ -102,8 +126,20 @@ def main():
                          lambda i: B.pwl_eval_backward(tg, xs[i % 3], gg[i % 3], ys[i % 3], dx[i % 3], dv),
                          verbose=True)
     print("backward best", best_b, "%.1f GB/s" % (16.0 * n / tb / 1e9), flush=True)
+    best = {B.KERNEL_FORWARD: best_f, B.KERNEL_BACKWARD: best_b}
+    if args.batch:
+        del xs, ys, gg, dx
+        specs = W.many_tables(T=4096, total_points=n, seed=2)
+        tabs = [B.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"])
+                for s in specs]
+        xb, offs = W.many_tables_points(specs, seed=0)
+        xb = torch.from_numpy(xb).to(dev)
+        yb = torch.empty_like(xb)
+        best_m, tm, _ = tune_batch(tabs, offs, xb, yb, verbose=True)
+        print("batch best", best_m, "%.1f GB/s" % (8.0 * xb.numel() / tm / 1e9), flush=True)
+        best[B.KERNEL_BATCH] = best_m
     if args.out:
-        save(args.out, {B.KERNEL_FORWARD: best_f, B.KERNEL_BACKWARD: best_b})
+        save(args.out, best)
 
 
 if __name__ == "__main__":

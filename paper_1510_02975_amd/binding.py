@@ -53,6 +53,14 @@ _SIGNATURES = {
     "pwl_locate": (_c_int32, [_vp, _vp, _vp, _c_int64, _vp]),
     "pwl_direct_gaussian": (_c_int32, [_vp, _vp, _c_int64, ctypes.c_float, ctypes.c_float, _c_int32, _vp]),
     "pwl_copy": (_c_int32, [_vp, _vp, _c_int64, _vp]),
+    "pwl_batch_create": (_c_int32, [ctypes.POINTER(_vp), _c_int32, ctypes.POINTER(_c_int64), _vp,
+                                    ctypes.POINTER(_vp)]),
+    "pwl_batch_eval": (_c_int32, [_vp, _vp, _vp, _vp]),
+    "pwl_batch_eval_backward": (_c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pwl_batch_capture": (_c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pwl_batch_replay": (_c_int32, [_vp, _vp]),
+    "pwl_batch_info": (_c_int32, [_vp, _ip, ctypes.POINTER(_c_int64), ctypes.POINTER(_c_int64), _ip, _ip, _ip, _ip]),
+    "pwl_batch_free": (None, [_vp]),
     "pwl_set_launch": (_c_int32, [_c_int32, _c_int32, _c_int32, _c_int32]),
     "pwl_get_launch": (_c_int32, [_c_int32, _ip, _ip, _ip]),
     "pwl_last_error": (ctypes.c_char_p, []),
@@ -256,6 +264,93 @@ def pwl_copy(src, dst=None, stream=None):
     _check(load_library().pwl_copy(_ptr(src, name="src"), _ptr(dst, name="dst"), src.numel(),
                                    _stream(stream)))
     return dst
+
+
+class Batch:
+    """Owner of a pwl_batch handle; keeps its tables alive."""
+
+    def __init__(self, handle, tables, offsets):
+        self.handle = handle
+        self.tables = list(tables)
+        self.offsets = list(int(o) for o in offsets)
+        self.T, self.npoints, self.dv_len, self.grid_fwd, self.grid_bwd, self.runs_fwd, self.runs_bwd = \
+            self.info()
+        self.dv_offsets = [0]
+        for t in self.tables:
+            self.dv_offsets.append(self.dv_offsets[-1] + t.N + 1)
+
+    def info(self):
+        T, gf, gb, rf, rb = _c_int32(), _c_int32(), _c_int32(), _c_int32(), _c_int32()
+        n, d = _c_int64(), _c_int64()
+        _check(load_library().pwl_batch_info(self.handle, ctypes.byref(T), ctypes.byref(n), ctypes.byref(d),
+                                             ctypes.byref(gf), ctypes.byref(gb), ctypes.byref(rf),
+                                             ctypes.byref(rb)))
+        return T.value, n.value, d.value, gf.value, gb.value, rf.value, rb.value
+
+    def free(self):
+        if self.handle is not None:
+            load_library().pwl_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pwl_batch_create(tables, offsets, stream=None):
+    """tables: list of Table; offsets: T+1 point offsets (host)."""
+    T = len(tables)
+    if len(offsets) != T + 1:
+        raise ValueError("offsets must have T + 1 entries")
+    handles = (_vp * T)(*[t.handle for t in tables])
+    offs = (_c_int64 * (T + 1))(*[int(o) for o in offsets])
+    out = _vp()
+    _check(load_library().pwl_batch_create(handles, T, offs, _stream(stream), ctypes.byref(out)))
+    return Batch(out, tables, offsets)
+
+
+def pwl_batch_eval(batch, x, y=None, stream=None):
+    if x.numel() != batch.npoints:
+        raise ValueError("x must hold the batch's %d points" % batch.npoints)
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load_library().pwl_batch_eval(batch.handle, _ptr(x, name="x"), _ptr(y, name="y"), _stream(stream)))
+    return y
+
+
+def pwl_batch_eval_backward(batch, x, g, y=None, dx=None, dv=None, stream=None, want=("y", "dx")):
+    if x.numel() != batch.npoints or g.numel() != batch.npoints:
+        raise ValueError("x and g must hold the batch's %d points" % batch.npoints)
+    if y is None and "y" in want:
+        y = torch.empty_like(x)
+    if dx is None and "dx" in want:
+        dx = torch.empty_like(x)
+    if dv is None:
+        dv = torch.empty(batch.dv_len, dtype=torch.float32, device=x.device)
+    _check(load_library().pwl_batch_eval_backward(
+        batch.handle, _ptr(x, name="x"), _ptr(g, name="g"), _ptr(y, name="y"), _ptr(dx, name="dx"),
+        _ptr(dv, name="dv"), _stream(stream)))
+    return y, dx, dv
+
+
+def pwl_batch_capture(batch, x, y=None, g=None, dx=None, dv=None, stream=None):
+    _check(load_library().pwl_batch_capture(
+        batch.handle, _ptr(x, name="x"), _ptr(g, name="g"), _ptr(y, name="y"), _ptr(dx, name="dx"),
+        _ptr(dv, name="dv"), _stream(stream)))
+
+
+def pwl_batch_replay(batch, stream=None):
+    _check(load_library().pwl_batch_replay(batch.handle, _stream(stream)))
+
+
+def pwl_batch_info(batch):
+    return batch.info()
+
+
+def pwl_batch_free(batch):
+    batch.free()
 
 
 KERNEL_FORWARD, KERNEL_BACKWARD, KERNEL_BATCH = 0, 1, 2

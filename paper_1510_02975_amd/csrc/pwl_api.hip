@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "pwl.h"
 #include "pwl_internal.h"
@@ -19,6 +20,16 @@ namespace pwl {
 hipError_t configure_build_kernels(int max_lds);
 hipError_t configure_eval_kernels(int max_lds);
 }  // namespace pwl
+
+struct pwl_batch {
+  int device;
+  int32_t T;
+  int64_t npoints;
+  pwl::BatchLaunch bl;
+  void* base;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
 
 struct pwl_table {
   int device;
@@ -68,6 +79,7 @@ pwl_status device_ready(int* dev_out, int* num_cu, int* max_lds = nullptr) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e == hipSuccess) e = pwl::configure_build_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_eval_kernels(lds);
+    if (e == hipSuccess) e = pwl::configure_batch_kernels(lds);
     g_num_cu[dev] = cu > 0 ? cu : 1;
     g_max_lds[dev] = lds;
     g_cfg_err[dev] = e;
@@ -404,6 +416,215 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
   if (st != PWL_OK) return st;
   PWL_HIP(pwl::launch_copy(src, dst, n, num_cu, static_cast<hipStream_t>(stream)));
   return PWL_OK;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+namespace {
+
+// Cuts points [0, P) into `grid` chunks of equal size (boundaries on multiples
+// of 4 points so chunks keep the 16-byte phase of the arrays) and lists the
+// table runs of every chunk.
+void plan_runs(const int64_t* offsets, int T, int64_t P, int grid, std::vector<pwl::BatchRun>* runs,
+               std::vector<int32_t>* run_begin) {
+  runs->clear();
+  run_begin->assign(grid + 1, 0);
+  int t = 0;
+  for (int w = 0; w < grid; ++w) {
+    (*run_begin)[w] = (int32_t)runs->size();
+    const int64_t c0 = (w == 0) ? 0 : ((int64_t)((__int128)P * w / grid) & ~(int64_t)3);
+    const int64_t c1 = (w == grid - 1) ? P : ((int64_t)((__int128)P * (w + 1) / grid) & ~(int64_t)3);
+    while (t < T && offsets[t + 1] <= c0) ++t;
+    for (int u = t; u < T && offsets[u] < c1; ++u) {
+      const int64_t b = std::max(c0, offsets[u]), e = std::min(c1, offsets[u + 1]);
+      if (b < e) runs->push_back(pwl::BatchRun{u, 0, b, e});
+    }
+  }
+  (*run_begin)[grid] = (int32_t)runs->size();
+}
+
+}  // namespace
+
+pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
+                            pwl_batch** out) {
+  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (tables == nullptr || offsets == nullptr) return fail(PWL_EINVAL, "tables and offsets must be non-NULL");
+  if (T < 1) return fail(PWL_EINVAL, "T must be >= 1");
+  if (offsets[0] != 0) return fail(PWL_EINVAL, "offsets[0] must be 0");
+  for (int i = 0; i < T; ++i) {
+    if (tables[i] == nullptr) return fail(PWL_EINVAL, "tables[%d] is NULL", i);
+    if (offsets[i + 1] < offsets[i]) return fail(PWL_EINVAL, "offsets must be non-decreasing (at %d)", i);
+  }
+  int dev = 0, num_cu = 1, max_lds = 0;
+  pwl_status st = device_ready(&dev, &num_cu, &max_lds);
+  if (st != PWL_OK) return st;
+  size_t lds_f = 0, lds_b = 0;
+  std::vector<pwl::BatchTable> hb(T);
+  int64_t dv_len = 0;
+  for (int i = 0; i < T; ++i) {
+    if (tables[i]->device != dev)
+      return fail(PWL_EINVAL, "tables[%d] lives on device %d, current is %d", i, tables[i]->device, dev);
+    hb[i].t = eval_view(tables[i]);
+    hb[i].dv_off = dv_len;
+    dv_len += tables[i]->bp.N + 1;
+    lds_f = std::max(lds_f, pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, false));
+    lds_b = std::max(lds_b, pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, true));
+  }
+  const pwl::LaunchConfig c = pwl::get_launch(PWL_KERNEL_BATCH);
+  auto grid_for = [&](size_t lds) {
+    const int by_lds = (int)std::max<size_t>(1, (size_t)max_lds / std::max<size_t>(lds, 1));
+    return num_cu * std::max(1, std::min(c.wg_per_cu, by_lds));
+  };
+  const int gf = grid_for(lds_f), gb = grid_for(lds_b);
+  const int64_t P = offsets[T];
+  std::vector<pwl::BatchRun> rf, rb;
+  std::vector<int32_t> bf, bb;
+  plan_runs(offsets, T, P, gf, &rf, &bf);
+  plan_runs(offsets, T, P, gb, &rb, &bb);
+  // one allocation: tables, forward runs and starts, backward runs and starts
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
+  const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
+  const size_t o_rf = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, rf.size()));
+  const size_t o_bf = take(sizeof(int32_t) * bf.size());
+  const size_t o_rb = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, rb.size()));
+  const size_t o_bb = take(sizeof(int32_t) * bb.size());
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, off);
+  if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
+  char* b = static_cast<char*>(base);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  e = hipMemcpyAsync(b + o_tab, hb.data(), sizeof(pwl::BatchTable) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !rf.empty())
+    e = hipMemcpyAsync(b + o_rf, rf.data(), sizeof(pwl::BatchRun) * rf.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b + o_bf, bf.data(), sizeof(int32_t) * bf.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !rb.empty())
+    e = hipMemcpyAsync(b + o_rb, rb.data(), sizeof(pwl::BatchRun) * rb.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b + o_bb, bb.data(), sizeof(int32_t) * bb.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(base);
+    return fail(PWL_EHIP, "batch upload failed: %s", hipGetErrorString(e));
+  }
+  pwl_batch* bt = new pwl_batch{};
+  bt->device = dev;
+  bt->T = T;
+  bt->npoints = P;
+  bt->base = base;
+  bt->bl.tables = reinterpret_cast<pwl::BatchTable*>(b + o_tab);
+  bt->bl.dv_len = dv_len;
+  bt->bl.fwd = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_rf), reinterpret_cast<int32_t*>(b + o_bf),
+                              gf, (int32_t)rf.size(), lds_f};
+  bt->bl.bwd = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_rb), reinterpret_cast<int32_t*>(b + o_bb),
+                              gb, (int32_t)rb.size(), lds_b};
+  *out = bt;
+  return PWL_OK;
+}
+
+namespace {
+
+pwl_status check_batch(const pwl_batch* bt) {
+  if (bt == nullptr) return fail(PWL_EINVAL, "batch is NULL");
+  int dev = 0;
+  pwl_status st = device_ready(&dev, nullptr);
+  if (st != PWL_OK) return st;
+  if (dev != bt->device)
+    return fail(PWL_EINVAL, "batch lives on device %d but device %d is current", bt->device, dev);
+  return PWL_OK;
+}
+
+pwl_status check_batch_args(const pwl_batch* bt, const float* x, const float* g, float* y, float* dx, float* dv) {
+  if (bt->npoints > 0 && x == nullptr) return fail(PWL_EINVAL, "x must be non-NULL");
+  if (g == nullptr) {
+    if (bt->npoints > 0 && y == nullptr) return fail(PWL_EINVAL, "y must be non-NULL");
+  } else {
+    if (dv == nullptr) return fail(PWL_EINVAL, "the batched backward needs dv");
+  }
+  (void)dx;
+  return PWL_OK;
+}
+
+}  // namespace
+
+pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream) {
+  pwl_status st = check_batch(bt);
+  if (st != PWL_OK) return st;
+  st = check_batch_args(bt, x, nullptr, y, nullptr, nullptr);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_batch(bt->bl, x, nullptr, y, nullptr, nullptr, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g, float* y, float* dx, float* dv,
+                                   void* stream) {
+  pwl_status st = check_batch(bt);
+  if (st != PWL_OK) return st;
+  if (g == nullptr) return fail(PWL_EINVAL, "g must be non-NULL");
+  st = check_batch_args(bt, x, g, y, dx, dv);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_batch(bt->bl, x, g, y, dx, dv, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_batch_capture(pwl_batch* bt, const float* x, const float* g, float* y, float* dx, float* dv,
+                             void* stream) {
+  pwl_status st = check_batch(bt);
+  if (st != PWL_OK) return st;
+  st = check_batch_args(bt, x, g, y, dx, dv);
+  if (st != PWL_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PWL_HIP(hipStreamSynchronize(s));
+  hipStream_t cs = nullptr;
+  PWL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t le = pwl::launch_batch(bt->bl, x, g, y, dx, dv, cs);
+    e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = le;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(PWL_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->graph = graph;
+  bt->exec = exec;
+  return PWL_OK;
+}
+
+pwl_status pwl_batch_replay(pwl_batch* bt, void* stream) {
+  pwl_status st = check_batch(bt);
+  if (st != PWL_OK) return st;
+  if (bt->exec == nullptr) return fail(PWL_EINVAL, "no captured graph: call pwl_batch_capture first");
+  PWL_HIP(hipGraphLaunch(bt->exec, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int64_t* dv_len, int32_t* grid_fwd,
+                          int32_t* grid_bwd, int32_t* runs_fwd, int32_t* runs_bwd) {
+  if (bt == nullptr) return fail(PWL_EINVAL, "batch is NULL");
+  if (T) *T = bt->T;
+  if (npoints) *npoints = bt->npoints;
+  if (dv_len) *dv_len = bt->bl.dv_len;
+  if (grid_fwd) *grid_fwd = bt->bl.fwd.grid;
+  if (grid_bwd) *grid_bwd = bt->bl.bwd.grid;
+  if (runs_fwd) *runs_fwd = bt->bl.fwd.nruns;
+  if (runs_bwd) *runs_bwd = bt->bl.bwd.nruns;
+  return PWL_OK;
+}
+
+void pwl_batch_free(pwl_batch* bt) {
+  if (bt == nullptr) return;
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  (void)hipFree(bt->base);
+  delete bt;
 }
 
 pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t wg_per_cu) {

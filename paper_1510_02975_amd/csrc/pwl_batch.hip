@@ -1,0 +1,195 @@
+// Batched evaluation of many tables of uneven size over uneven point counts
+// in one persistent launch.
+//
+// The points of all tables are concatenated (table t owns [off_t, off_{t+1})).
+// The host cuts the concatenation into one contiguous, equally sized chunk
+// per workgroup and lists, per workgroup, the (table, begin, end) runs its
+// chunk covers.  A workgroup walks its runs in order, re-staging the LDS
+// table only when the table changes, and streams each run with the same
+// vectorised body as the single-table evaluator.  The fused backward keeps a
+// workgroup's dL/dv of the current table in FP64 LDS and flushes it with
+// global FP32 atomics into the concatenated gradient (table t at dv_off_t)
+// whenever the table changes and at the end.
+#include <hip/hip_runtime.h>
+
+#include "pwl_internal.h"
+#include "pwl_stream.h"
+
+namespace pwl {
+
+namespace {
+
+using namespace stream;
+
+template <int U>
+__device__ __forceinline__ void batch_fwd_run(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+                                              float* __restrict__ y, int64_t b, int64_t e, bool vec) {
+  switch (t.meta[1]) {
+    case 0:
+    case 1: fwd_range<U, 1>(t, s, x, y, b, e, vec, 0, 1); break;
+    case 2: fwd_range<U, 2>(t, s, x, y, b, e, vec, 0, 1); break;
+    case 3: fwd_range<U, 3>(t, s, x, y, b, e, vec, 0, 1); break;
+    case 4: fwd_range<U, 4>(t, s, x, y, b, e, vec, 0, 1); break;
+    default: fwd_range<U, 0>(t, s, x, y, b, e, vec, 0, 1); break;
+  }
+}
+
+template <int U>
+__global__ __launch_bounds__(1024) void k_batch_fwd(const BatchTable* __restrict__ tabs,
+                                                    const BatchRun* __restrict__ runs,
+                                                    const int32_t* __restrict__ run_begin,
+                                                    const float* __restrict__ x, float* __restrict__ y,
+                                                    int vec) {
+  extern __shared__ float4 lds_f4[];
+  const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
+  int cur = -1;
+  EvalTable t;
+  Smem s;
+  for (int r = r0; r < r1; ++r) {
+    const BatchRun run = runs[r];
+    if (run.table != cur) {
+      __syncthreads();   // every thread is done with the previous table
+      t = tabs[run.table].t;
+      s = carve(lds_f4, t.N, t.K, false);
+      stage_table(t, nullptr, s);
+      __syncthreads();
+      cur = run.table;
+    }
+    batch_fwd_run<U>(t, s, x, y, run.begin, run.end, vec != 0);
+  }
+}
+
+template <int U, bool WY, bool WDX>
+__device__ __forceinline__ void batch_bwd_run(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+                                              const float* __restrict__ g, float* __restrict__ y,
+                                              float* __restrict__ dx, int64_t b, int64_t e, bool vec) {
+  using B = Bwd<U, WY, WDX, true>;
+  switch (t.meta[1]) {
+    case 0:
+    case 1: B::template range<1>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+    case 2: B::template range<2>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+    case 3: B::template range<3>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+    case 4: B::template range<4>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+    default: B::template range<0>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+  }
+}
+
+__device__ __forceinline__ void flush_dv(const Smem& s, int N, float* __restrict__ dv) {
+  for (int k = threadIdx.x; k <= N; k += blockDim.x) {
+    const float v = (float)s.dv[k];
+    if (v != 0.0f) unsafeAtomicAdd(dv + k, v);
+  }
+}
+
+template <int U, bool WY, bool WDX>
+__global__ __launch_bounds__(1024) void k_batch_bwd(const BatchTable* __restrict__ tabs,
+                                                    const BatchRun* __restrict__ runs,
+                                                    const int32_t* __restrict__ run_begin,
+                                                    const float* __restrict__ x, const float* __restrict__ g,
+                                                    float* __restrict__ y, float* __restrict__ dx,
+                                                    float* __restrict__ dv, int vec) {
+  extern __shared__ float4 lds_f4[];
+  const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
+  int cur = -1;
+  EvalTable t;
+  Smem s;
+  int64_t dv_off = 0;
+  for (int r = r0; r < r1; ++r) {
+    const BatchRun run = runs[r];
+    if (run.table != cur) {
+      __syncthreads();   // every thread is done with the previous table
+      if (cur >= 0) {
+        flush_dv(s, t.N, dv + dv_off);
+        __syncthreads();
+      }
+      t = tabs[run.table].t;
+      dv_off = tabs[run.table].dv_off;
+      s = carve(lds_f4, t.N, t.K, true);
+      stage_table(t, nullptr, s);
+      for (int k = threadIdx.x; k <= t.N; k += blockDim.x) s.dv[k] = 0.0;
+      __syncthreads();
+      cur = run.table;
+    }
+    batch_bwd_run<U, WY, WDX>(t, s, x, g, y, dx, run.begin, run.end, vec != 0);
+  }
+  if (cur >= 0) {
+    __syncthreads();
+    flush_dv(s, t.N, dv + dv_off);
+  }
+}
+
+__global__ void k_batch_zero(float* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+inline bool same_phase(const void* a, const void* b) {
+  return b == nullptr || ((reinterpret_cast<uintptr_t>(a) ^ reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
+                        float* dv, hipStream_t s) {
+  const LaunchConfig c = get_launch(PWL_KERNEL_BATCH);
+  const bool backward = g != nullptr;
+  const BatchPlan& p = backward ? bl.bwd : bl.fwd;
+  const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
+                   (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
+  const int v = vec ? 1 : 0;
+  const dim3 grid(p.grid), block(c.block);
+  if (!backward) {
+    switch (c.unroll) {
+      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
+      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
+      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
+    }
+    return hipGetLastError();
+  }
+  const int64_t zgrid = std::min<int64_t>(1024, (bl.dv_len + 255) / 256);
+  hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::max<int64_t>(1, zgrid)), dim3(256), 0, s, dv, bl.dv_len);
+  const int key = (y != nullptr ? 2 : 0) | (dx != nullptr ? 1 : 0);
+#define PWL_BB(UU, A, B)                                                                              \
+  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, g, \
+                     y, dx, dv, v)
+#define PWL_BB_U(UU)                             \
+  switch (key) {                                 \
+    case 0: PWL_BB(UU, false, false); break;     \
+    case 1: PWL_BB(UU, false, true); break;      \
+    case 2: PWL_BB(UU, true, false); break;      \
+    default: PWL_BB(UU, true, true); break;      \
+  }
+  switch (c.unroll) {
+    case 1: PWL_BB_U(1) break;
+    case 2: PWL_BB_U(2) break;
+    default: PWL_BB_U(4) break;
+  }
+#undef PWL_BB_U
+#undef PWL_BB
+  return hipGetLastError();
+}
+
+hipError_t configure_batch_kernels(int max_lds) {
+  const int lim = max_lds < 160 * 1024 ? max_lds : 160 * 1024;
+  hipError_t e = hipSuccess;
+#define PWL_ATTR(K)                                                                        \
+  e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, lim); \
+  if (e != hipSuccess) return e;
+  PWL_ATTR(k_batch_fwd<1>)
+  PWL_ATTR(k_batch_fwd<2>)
+  PWL_ATTR(k_batch_fwd<4>)
+#define PWL_ATTR_U(UU)                          \
+  PWL_ATTR((k_batch_bwd<UU, false, false>))     \
+  PWL_ATTR((k_batch_bwd<UU, false, true>))      \
+  PWL_ATTR((k_batch_bwd<UU, true, false>))      \
+  PWL_ATTR((k_batch_bwd<UU, true, true>))
+  PWL_ATTR_U(1)
+  PWL_ATTR_U(2)
+  PWL_ATTR_U(4)
+#undef PWL_ATTR_U
+#undef PWL_ATTR
+  return hipSuccess;
+}
+
+}  // namespace pwl

@@ -5,13 +5,13 @@
 //     k_invert_knots     FP64 prefix of those sums, targets i S_M / N, linear inversion;
 //                        per knot also its map cell and, for the interpolant, f(x_i)
 //   uniform partition (Sec. IV): k_uniform_knots writes the knots, cells and values
-//   projection values (Sec. II-B2):
-//     k_segments         FP32 Gauss-Legendre integrals of f against both hats of every
-//                        segment, one lane per (segment, node)
 //   every table:
-//     k_finalize         one workgroup: the uniform index map, the FP64 solve of
-//                        M c = b (parallel cyclic reduction), knot-collapse check and
-//                        the packed records {x_k, v_k, slope_k, 1/h_k}
+//     k_segments         per segment: its cells of the uniform index map, the
+//                        knot-collapse check, the deepest cell; for the projection
+//                        (Sec. II-B2) FP32 Gauss-Legendre integrals of f against both
+//                        hats, one lane per (segment, node)
+//     k_finalize         one workgroup: the FP64 solve of M c = b (parallel cyclic
+//                        reduction) and the packed records {x_k, v_k, slope_k, 1/h_k}
 #include <hip/hip_runtime.h>
 
 #include "pwl_func.h"
@@ -85,7 +85,10 @@ __global__ __launch_bounds__(kScanThreads) void k_density_totals(BuildParams bp,
   const double tot = scan_block_cells(bp, blockIdx.x, s_d, s_tp, nullptr);
   if (threadIdx.x == 0) {
     td.totals[blockIdx.x] = tot;
-    if (blockIdx.x == 0) td.status[0] = 0u;
+    if (blockIdx.x == 0) {
+      td.status[0] = 0u;
+      td.status[1] = 0u;
+    }
   }
 }
 
@@ -192,16 +195,45 @@ __global__ __launch_bounds__(kScanThreads) void k_invert_knots(BuildParams bp, T
 __global__ __launch_bounds__(kBuildThreads) void k_uniform_knots(BuildParams bp, TableDev td) {
   const int k = blockIdx.x * kBuildThreads + threadIdx.x;
   if (k <= bp.N) emit_knot(bp, td, k, uniform_knot(bp, k));
-  if (k == 0) td.status[0] = 0u;
+  if (k == 0) {
+    td.status[0] = 0u;
+    td.status[1] = 0u;
+  }
 }
 
-// <f, phi_k> pieces of every segment by Gauss-Legendre: lane q of a
-// 16-lane group evaluates node q of segment k; the group reduces its
-// (1 - t) f and t f products with cross-lane shuffles.
+// Per segment k (between knots k and k+1), once the knots are known:
+//  - the uniform index map lo[u] = #{interior knots with cell < u}: segment k
+//    owns the cells (cell(x_k), cell(x_{k+1})], with cell(x_0) = -1 and
+//    cell(x_N) = K - 1, so every cell is written exactly once when the knots
+//    increase (k_finalize clears the map of a collapsed table);
+//  - the knot-collapse check x_{k+1} > x_k;
+//  - the longest run of interior knots sharing one cell (the evaluator's
+//    unrolled compare depth);
+//  - for the projection, <f, phi_k> pieces by Gauss-Legendre: lane q of a
+//    16-lane group evaluates node q and the group reduces its (1 - t) f and
+//    t f products with cross-lane shuffles.
+template <int LANES>
 __global__ __launch_bounds__(kBuildThreads) void k_segments(BuildParams bp, TableDev td) {
   const int gid = blockIdx.x * kBuildThreads + threadIdx.x;
-  const int k = gid / kGaussPoints;
-  const int q = gid % kGaussPoints;
+  const int k = gid / LANES;
+  const int q = gid % LANES;
+  int run = 0;
+  if (k < bp.N && q == 0) {
+    const int u0 = (k == 0) ? -1 : td.ucell[k];
+    const int u1 = (k + 1 == bp.N) ? bp.K - 1 : td.ucell[k + 1];
+    for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
+    if (!(td.knots[k + 1] > td.knots[k])) atomicOr(td.status, (uint32_t)PWL_FLAG_KNOTS_COLLAPSED);
+    if (k >= 1 && (k == 1 || td.ucell[k - 1] != u0)) {   // first interior knot of its cell
+      run = 1;
+      while (k + run <= bp.N - 1 && td.ucell[k + run] == u0) ++run;
+    }
+  }
+  if (k == 0 && q == 0) td.lo[bp.K] = (uint16_t)(bp.N - 1);
+  // one atomic per wavefront for the deepest cell
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) run = max(run, __shfl_xor(run, m));
+  if ((threadIdx.x & 63) == 0 && run > 0) atomicMax(td.status + 1, (uint32_t)run);
+  if (LANES == 1) return;
   float sl = 0.0f, sr = 0.0f, h = 0.0f;
   if (k < bp.N) {
     const float xk = td.knots[k];
@@ -212,9 +244,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_segments(BuildParams bp, Tabl
     sr = t * fq;
   }
 #pragma unroll
-  for (int m = kGaussPoints / 2; m >= 1; m >>= 1) {
-    sl += __shfl_xor(sl, m, kGaussPoints);
-    sr += __shfl_xor(sr, m, kGaussPoints);
+  for (int m = LANES / 2; m >= 1; m >>= 1) {
+    sl += __shfl_xor(sl, m, LANES);
+    sr += __shfl_xor(sr, m, LANES);
   }
   if (k < bp.N && q == 0) {
     td.quad_l[k] = h * sl;
@@ -233,46 +265,12 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   double* B = A + n;
   double* Cu = B + n;
   double* D = Cu + n;
-  int* s_uc = reinterpret_cast<int*>(D + n);   // map cells of the knots, [N + 1]
-  __shared__ int s_collapsed, s_maxc;
-  if (tid == 0) {
-    s_collapsed = 0;
-    s_maxc = 0;
-  }
-  __syncthreads();
-
-  // 1. knot-collapse check on the FP32 knots; the knots' cells to LDS
-  int bad = 0;
-  for (int k = tid; k < N; k += kFinalizeThreads)
-    if (!(td.knots[k + 1] > td.knots[k])) bad = 1;
-  if (bad) atomicOr(&s_collapsed, 1);
-  for (int k = tid; k <= N; k += kFinalizeThreads)
-    s_uc[k] = (k == 0) ? -1 : ((k == N) ? bp.K - 1 : td.ucell[k]);
-  __syncthreads();
-  const bool collapsed = s_collapsed != 0;
-
-  // 2. uniform index map lo[u] = #{interior knots with cell < u}: segment k
-  // (between knots k and k+1) owns the cells (cell(x_k), cell(x_{k+1})], with
-  // cell(x_0) = -1 and cell(x_N) = K - 1, so every cell is written once.
-  // The longest run of interior knots sharing one cell is the evaluator's
-  // unrolled compare depth.  A collapsed table (evaluated as NaN) gets an
-  // all-zero map so no lookup leaves the table.
-  int my_max = 0;
-  if (!collapsed) {
-    for (int k = tid; k < N; k += kFinalizeThreads) {
-      const int u0 = s_uc[k], u1 = s_uc[k + 1];
-      for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
-      if (k >= 1 && (k == 1 || s_uc[k - 1] != u0)) {   // first interior knot of its cell
-        int run = 1;
-        while (k + run <= N - 1 && s_uc[k + run] == u0) ++run;
-        my_max = max(my_max, run);
-      }
-    }
-  } else {
+  const bool collapsed = (td.status[0] & PWL_FLAG_KNOTS_COLLAPSED) != 0u;
+  if (collapsed) {
+    // The evaluators never leave the table through an all-zero map; the
+    // records below are NaN.
     for (int u = tid; u < bp.K; u += kFinalizeThreads) td.lo[u] = 0;
   }
-  if (tid == 0) td.lo[bp.K] = (uint16_t)(N - 1);
-  if (my_max > 0) atomicMax(&s_maxc, my_max);
 
   // 3. vertex values
   if (bp.values == PWL_PROJ) {
@@ -363,13 +361,6 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     }
     td.rec[k] = r;
   }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t st = td.status[0];
-    if (collapsed) st |= PWL_FLAG_KNOTS_COLLAPSED;
-    td.status[0] = st;
-    td.status[1] = (uint32_t)s_maxc;
-  }
 }
 
 }  // namespace
@@ -384,7 +375,10 @@ hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s
   }
   if (bp.values == PWL_PROJ) {
     const int nb = (bp.N * kGaussPoints + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_segments, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
+    hipLaunchKernelGGL(k_segments<kGaussPoints>, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
+  } else {
+    const int nb = (bp.N + kBuildThreads - 1) / kBuildThreads;
+    hipLaunchKernelGGL(k_segments<1>, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), finalize_lds_bytes(bp.N), s, bp, td);
   return hipGetLastError();

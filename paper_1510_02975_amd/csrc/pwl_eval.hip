@@ -1,7 +1,7 @@
 // Streaming evaluation kernels (Algorithm 1, Sec. IV) for gfx950.
 //
 // Every workgroup stages the whole table in LDS once - packed records
-// {x_k, v_k, slope_k, 1/h_k}, the interior knots (+inf padded) and the
+// {x_k, v_k, slope_k, 1/h_k}, the interior knots (NaN padded) and the
 // uniform index map - and then streams its share of the points with 16-byte
 // non-temporal loads and stores, U vectors per thread in flight.  The path is
 // a memory-bound gather (8 bytes per point forward, 16 fused forward and
@@ -15,254 +15,50 @@
 
 #include "pwl_internal.h"
 #include "pwl_locate.h"
+#include "pwl_stream.h"
 
 namespace pwl {
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-
 constexpr int kStreamUnroll = 4;    // float4 vectors per thread per iteration (baselines)
 constexpr size_t kLdsPerCU = 160 * 1024;
 
-struct Smem {
-  float4* rec;      // [N]           {x_k, v_k, slope_k, 1/h_k}
-  float* knot;      // [N + pad]     knot[k] = x_k for 1 <= k <= N-1, NaN elsewhere
-  uint16_t* lo;     // [K + 1]       lo[u] = #{interior knots in cells < u}; lo[K] = N - 1
-  double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
-};
-
-__device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
-  Smem s;
-  s.rec = reinterpret_cast<float4*>(base);
-  s.knot = reinterpret_cast<float*>(s.rec + N);
-  s.lo = reinterpret_cast<uint16_t*>(s.knot + N + kKnotPad);
-  s.dv = backward ? reinterpret_cast<double*>(
-                        (reinterpret_cast<uintptr_t>(s.lo + ((K + 2) & ~1)) + 7) & ~(uintptr_t)7)
-                  : nullptr;
-  return s;
-}
-
-// Copy the table into LDS.  With v_override the vertex values come from the
-// caller and slopes are re-derived as (v_{k+1} - v_k) / h_k in FP32.  The
-// knot sentinels are NaN so that every compare against them is false, even
-// for x = +inf.
-__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo,
-                                            const Smem& s) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < t.N; k += nt) {
-    float4 r = t.rec[k];
-    if (vo != nullptr) {
-      const float v0 = vo[k], v1 = vo[k + 1];
-      r.y = v0;
-      r.z = (v1 - v0) * r.w;
-    }
-    s.rec[k] = r;
-  }
-  const float qnan = __builtin_nanf("");
-  for (int k = tid; k < t.N + kKnotPad; k += nt)
-    s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
-  for (int u = tid; u <= t.K; u += nt) s.lo[u] = t.lo[u];
-}
-
-__device__ __forceinline__ float clamp_nan(float x, float a, float b) {
-  return (x < a) ? a : ((x > b) ? b : x);   // NaN passes through
-}
-
-// Segment of x when no map cell holds more than MAXC knots: compare x with
-// the MAXC knots that follow lo[cell(x)].  Knots beyond the cell's own are
-// greater than x (they lie in later cells) and the sentinels are NaN, so the
-// extra compares are false; the count of true compares is exact.
-template <int MAXC>
-__device__ __forceinline__ int locate_fixed(float x, const EvalTable& t, const Smem& s) {
-  const int u = map_cell(x, t.a32, t.scale32, t.K);
-  const int lo = s.lo[u];
-  int seg = lo;
-#pragma unroll
-  for (int j = 1; j <= MAXC; ++j) seg += (x >= s.knot[lo + j]) ? 1 : 0;
-  return seg;
-}
-
-// Any number of knots per cell: the count is lo[u+1] - lo[u].
-__device__ __forceinline__ int locate_any(float x, const EvalTable& t, const Smem& s) {
-  const int u = map_cell(x, t.a32, t.scale32, t.K);
-  const int lo = s.lo[u];
-  const int cnt = (int)s.lo[u + 1] - lo;
-  int seg = lo;
-  for (int j = 1; j <= cnt; ++j) seg += (x >= s.knot[lo + j]) ? 1 : 0;
-  return seg;
-}
-
-template <int MAXC>
-__device__ __forceinline__ int locate(float x, const EvalTable& t, const Smem& s) {
-  if (MAXC > 0) return locate_fixed<MAXC>(x, t, s);
-  return locate_any(x, t, s);
-}
-
-template <int MAXC>
-__device__ __forceinline__ float eval_point(float x, const EvalTable& t, const Smem& s) {
-  const int seg = locate<MAXC>(x, t, s);
-  const float4 r = s.rec[seg];
-  return fmaf(clamp_nan(x, t.a32, t.b32) - r.x, r.z, r.y);
-}
-
-template <int MAXC, bool WY, bool WDX, bool WDV>
-__device__ __forceinline__ void backward_point(float x, float g, const EvalTable& t, const Smem& s,
-                                               float& y, float& dx) {
-  const int seg = locate<MAXC>(x, t, s);
-  const float4 r = s.rec[seg];
-  const float d = clamp_nan(x, t.a32, t.b32) - r.x;
-  if (WY) y = fmaf(d, r.z, r.y);
-  if (WDX) {
-    const bool inside = (x >= t.a32) && (x <= t.b32);
-    dx = inside ? g * r.z : ((x != x) ? x : 0.0f);
-  }
-  if (WDV) {
-    if (x == x) {
-      // The workgroup's dL/dv lives in LDS as FP64: FP64 LDS atomic adds run
-      // at full rate on gfx950 (FP32 ones take a slow path) and keep the
-      // per-workgroup sums exact to FP32 output precision.  Workgroup scope,
-      // relaxed: no point has to wait for the thread's outstanding stores.
-      const float w1 = (d * r.w) * g;   // delta g
-      __hip_atomic_fetch_add(s.dv + seg, (double)(g - w1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(s.dv + seg + 1, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-  }
-}
+using namespace stream;
 
 // Points [4 n4, n) (or all of them when the arrays are not 16-byte aligned,
-// n4 = 0) go through this grid-strided scalar loop.
+// n4 = 0) of the baseline kernels go through this grid-strided scalar loop.
 #define PWL_SCALAR_TAIL(...)                                                                \
   for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;         \
        i += (int64_t)gridDim.x * blockDim.x) {                                              \
     __VA_ARGS__;                                                                            \
   }
 
-// One grid-stride iteration over U float4 vectors per thread: all loads,
-// then all table lookups, then all stores.  Full iterations run unguarded so
-// the compiler can count outstanding memory operations exactly (a guarded
-// load makes every later wait a wait for all stores); the last, partial
-// iteration of a thread is guarded.
-template <int U, int MAXC, bool GUARD>
-__device__ __forceinline__ void fwd_iter(const EvalTable& t, const Smem& s, const v4f* __restrict__ x4,
-                                         v4f* __restrict__ y4, int64_t base, int64_t bs, int64_t n4) {
-  v4f xv[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = base + u * bs;
-    if (!GUARD || i < n4) xv[u] = __builtin_nontemporal_load(x4 + i);
-  }
-  v4f yv[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    yv[u].x = eval_point<MAXC>(xv[u].x, t, s);
-    yv[u].y = eval_point<MAXC>(xv[u].y, t, s);
-    yv[u].z = eval_point<MAXC>(xv[u].z, t, s);
-    yv[u].w = eval_point<MAXC>(xv[u].w, t, s);
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = base + u * bs;
-    if (!GUARD || i < n4) __builtin_nontemporal_store(yv[u], y4 + i);
-  }
-}
-
-template <int U, int MAXC>
-__device__ __forceinline__ void fwd_stream(const EvalTable& t, const Smem& s, const float* __restrict__ x,
-                                           float* __restrict__ y, int64_t n4, int64_t n) {
-  const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x);
-  v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y);
-  const int64_t bs = blockDim.x;
-  const int64_t stride = (int64_t)gridDim.x * bs * U;
-  int64_t base = (int64_t)blockIdx.x * bs * U + threadIdx.x;
-  for (; base + (U - 1) * bs < n4; base += stride) fwd_iter<U, MAXC, false>(t, s, x4, y4, base, bs, n4);
-  if (base < n4) fwd_iter<U, MAXC, true>(t, s, x4, y4, base, bs, n4);
-  PWL_SCALAR_TAIL(y[i] = eval_point<MAXC>(x[i], t, s))
-}
-
 template <int U>
 __global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __restrict__ vo,
                                                    const float* __restrict__ x,
-                                                   float* __restrict__ y, int64_t n4, int64_t n) {
+                                                   float* __restrict__ y, int64_t n, int vec) {
   extern __shared__ float4 lds_f4[];
   const Smem s = carve(lds_f4, t.N, t.K, false);
   stage_table(t, vo, s);
   __syncthreads();
+  const int64_t blk = blockIdx.x, nblk = gridDim.x;
   switch (t.meta[1]) {
     case 0:
-    case 1: fwd_stream<U, 1>(t, s, x, y, n4, n); break;
-    case 2: fwd_stream<U, 2>(t, s, x, y, n4, n); break;
-    case 3: fwd_stream<U, 3>(t, s, x, y, n4, n); break;
-    case 4: fwd_stream<U, 4>(t, s, x, y, n4, n); break;
-    default: fwd_stream<U, 0>(t, s, x, y, n4, n); break;
+    case 1: fwd_range<U, 1>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
+    case 2: fwd_range<U, 2>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
+    case 3: fwd_range<U, 3>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
+    case 4: fwd_range<U, 4>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
+    default: fwd_range<U, 0>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
   }
 }
-
-template <int U, bool WY, bool WDX, bool WDV>
-struct Bwd {
-  template <int MAXC, bool GUARD>
-  __device__ __forceinline__ static void iter(const EvalTable& t, const Smem& s, const v4f* __restrict__ x4,
-                                              const v4f* __restrict__ g4, v4f* __restrict__ y4,
-                                              v4f* __restrict__ dx4, int64_t base, int64_t bs, int64_t n4) {
-    v4f xv[U], gv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + u * bs;
-      if (!GUARD || i < n4) {
-        xv[u] = __builtin_nontemporal_load(x4 + i);
-        gv[u] = __builtin_nontemporal_load(g4 + i);
-      }
-    }
-    v4f yv[U], dxv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (GUARD && base + u * bs >= n4) continue;
-      float yy = 0.0f, dd = 0.0f;
-      backward_point<MAXC, WY, WDX, WDV>(xv[u].x, gv[u].x, t, s, yy, dd); yv[u].x = yy; dxv[u].x = dd;
-      backward_point<MAXC, WY, WDX, WDV>(xv[u].y, gv[u].y, t, s, yy, dd); yv[u].y = yy; dxv[u].y = dd;
-      backward_point<MAXC, WY, WDX, WDV>(xv[u].z, gv[u].z, t, s, yy, dd); yv[u].z = yy; dxv[u].z = dd;
-      backward_point<MAXC, WY, WDX, WDV>(xv[u].w, gv[u].w, t, s, yy, dd); yv[u].w = yy; dxv[u].w = dd;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + u * bs;
-      if (!GUARD || i < n4) {
-        if (WY) __builtin_nontemporal_store(yv[u], y4 + i);
-        if (WDX) __builtin_nontemporal_store(dxv[u], dx4 + i);
-      }
-    }
-  }
-
-  template <int MAXC>
-  __device__ __forceinline__ static void stream(const EvalTable& t, const Smem& s,
-                                                const float* __restrict__ x, const float* __restrict__ g,
-                                                float* __restrict__ y, float* __restrict__ dx, int64_t n4,
-                                                int64_t n) {
-    const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x);
-    const v4f* __restrict__ g4 = reinterpret_cast<const v4f*>(g);
-    v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y);
-    v4f* __restrict__ dx4 = reinterpret_cast<v4f*>(dx);
-    const int64_t bs = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bs * U;
-    int64_t base = (int64_t)blockIdx.x * bs * U + threadIdx.x;
-    for (; base + (U - 1) * bs < n4; base += stride)
-      iter<MAXC, false>(t, s, x4, g4, y4, dx4, base, bs, n4);
-    if (base < n4) iter<MAXC, true>(t, s, x4, g4, y4, dx4, base, bs, n4);
-    PWL_SCALAR_TAIL({
-      float yy = 0.0f, dd = 0.0f;
-      backward_point<MAXC, WY, WDX, WDV>(x[i], g[i], t, s, yy, dd);
-      if (WY) y[i] = yy;
-      if (WDX) dx[i] = dd;
-    })
-  }
-};
 
 template <int U, bool WY, bool WDX, bool WDV>
 __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __restrict__ vo,
                                                    const float* __restrict__ x,
                                                    const float* __restrict__ g,
                                                    float* __restrict__ y, float* __restrict__ dx,
-                                                   float* __restrict__ dv, int64_t n4, int64_t n) {
+                                                   float* __restrict__ dv, int64_t n, int vec) {
   extern __shared__ float4 lds_f4[];
   const Smem s = carve(lds_f4, t.N, t.K, WDV);
   stage_table(t, vo, s);
@@ -270,13 +66,14 @@ __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __r
     for (int k = threadIdx.x; k <= t.N; k += blockDim.x) s.dv[k] = 0.0;
   __syncthreads();
   using B = Bwd<U, WY, WDX, WDV>;
+  const int64_t blk = blockIdx.x, nblk = gridDim.x;
   switch (t.meta[1]) {
     case 0:
-    case 1: B::template stream<1>(t, s, x, g, y, dx, n4, n); break;
-    case 2: B::template stream<2>(t, s, x, g, y, dx, n4, n); break;
-    case 3: B::template stream<3>(t, s, x, g, y, dx, n4, n); break;
-    case 4: B::template stream<4>(t, s, x, g, y, dx, n4, n); break;
-    default: B::template stream<0>(t, s, x, g, y, dx, n4, n); break;
+    case 1: B::template range<1>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
+    case 2: B::template range<2>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
+    case 3: B::template range<3>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
+    case 4: B::template range<4>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
+    default: B::template range<0>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
   }
   if (WDV) {
     __syncthreads();
@@ -369,6 +166,12 @@ __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, flo
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// The vector path needs every point array at the same 16-byte phase (a
+// slice of aligned arrays qualifies); the head and tail points are scalar.
+inline bool same_phase(const void* a, const void* b) {
+  return b == nullptr || ((reinterpret_cast<uintptr_t>(a) ^ reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
+}
+
 // Launch shape of a streaming evaluation kernel: `wg_per_cu` workgroups of
 // `block` threads per CU (fewer if the table's LDS does not allow that
 // many), each thread handling `unroll` float4 vectors per iteration, and
@@ -410,24 +213,25 @@ LaunchConfig get_launch(int kernel) { return g_launch[kernel]; }
 
 hipError_t launch_eval(const EvalTable& t, const float* vo, const float* x, float* y, int64_t n,
                        int num_cu, hipStream_t s) {
-  const int64_t n4 = (aligned16(x) && aligned16(y)) ? n / 4 : 0;
+  const bool vec = same_phase(x, y) && (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const LaunchConfig c = g_launch[0];
-  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, false), n4, n, num_cu);
+  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, false), vec ? n / 4 : 0, n, num_cu);
+  const int v = vec ? 1 : 0;
   switch (c.unroll) {
-    case 1: hipLaunchKernelGGL(k_eval_fwd<1>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n4, n); break;
-    case 2: hipLaunchKernelGGL(k_eval_fwd<2>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n4, n); break;
-    default: hipLaunchKernelGGL(k_eval_fwd<4>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n4, n); break;
+    case 1: hipLaunchKernelGGL(k_eval_fwd<1>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
+    case 2: hipLaunchKernelGGL(k_eval_fwd<2>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
+    default: hipLaunchKernelGGL(k_eval_fwd<4>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
   }
   return hipGetLastError();
 }
 
 template <int U>
 void launch_bwd_u(const LaunchShape& ls, int key, const EvalTable& t, const float* vo, const float* x,
-                  const float* g, float* y, float* dx, float* dv, int64_t n4, int64_t n, hipStream_t s) {
+                  const float* g, float* y, float* dx, float* dv, int64_t n, int vec, hipStream_t s) {
 #define PWL_BWD_CASE(K, A, B, C)                                                                 \
   case K:                                                                                        \
     hipLaunchKernelGGL((k_eval_bwd<U, A, B, C>), dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, \
-                       x, g, y, dx, dv, n4, n);                                                  \
+                       x, g, y, dx, dv, n, vec);                                                 \
     break;
   switch (key) {
     PWL_BWD_CASE(1, false, false, true)
@@ -444,19 +248,19 @@ void launch_bwd_u(const LaunchShape& ls, int key, const EvalTable& t, const floa
 
 hipError_t launch_eval_backward(const EvalTable& t, const float* vo, const float* x, const float* g,
                                 float* y, float* dx, float* dv, int64_t n, int num_cu, hipStream_t s) {
-  const bool al = aligned16(x) && aligned16(g) && (y == nullptr || aligned16(y)) &&
-                  (dx == nullptr || aligned16(dx));
-  const int64_t n4 = al ? n / 4 : 0;
+  const bool vec = same_phase(x, g) && same_phase(x, y) && same_phase(x, dx) &&
+                   (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const bool wdv = dv != nullptr;
   const LaunchConfig c = g_launch[1];
-  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, wdv), n4, n, num_cu);
+  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, wdv), vec ? n / 4 : 0, n, num_cu);
   const int key = (y != nullptr ? 4 : 0) | (dx != nullptr ? 2 : 0) | (wdv ? 1 : 0);
   if (key == 0) return hipErrorInvalidValue;
   if (wdv) hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, s, dv, (int64_t)t.N + 1);
+  const int v = vec ? 1 : 0;
   switch (c.unroll) {
-    case 1: launch_bwd_u<1>(ls, key, t, vo, x, g, y, dx, dv, n4, n, s); break;
-    case 2: launch_bwd_u<2>(ls, key, t, vo, x, g, y, dx, dv, n4, n, s); break;
-    default: launch_bwd_u<4>(ls, key, t, vo, x, g, y, dx, dv, n4, n, s); break;
+    case 1: launch_bwd_u<1>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
+    case 2: launch_bwd_u<2>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
+    default: launch_bwd_u<4>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
   }
   return hipGetLastError();
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "pwl.h"
 
 namespace pwl {
@@ -74,10 +76,8 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
   return b;
 }
 
-// PCR rows (4 FP64 diagonals) and the knots' map cells.
-inline size_t finalize_lds_bytes(int N) {
-  return 4 * sizeof(double) * (size_t)(N + 1) + sizeof(int) * (size_t)(N + 1);
-}
+// PCR rows: 4 FP64 arrays.
+inline size_t finalize_lds_bytes(int N) { return 4 * sizeof(double) * (size_t)(N + 1); }
 
 // Number of map cells for a table of N segments: two per segment on a uniform
 // partition (each cell then holds at most one knot), four on the optimal one.
@@ -98,6 +98,36 @@ struct LaunchConfig {
 
 hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu);
 LaunchConfig get_launch(int kernel);
+
+// ---- batched evaluation ----------------------------------------------------
+struct BatchTable {          // one table of a batch, as the device sees it
+  EvalTable t;
+  int64_t dv_off;            // first of its N + 1 entries in the concatenated dL/dv
+};
+
+struct BatchRun {            // points [begin, end) of one table, handled by one workgroup
+  int32_t table;
+  int32_t pad;
+  int64_t begin, end;
+};
+
+struct BatchPlan {           // the runs of every workgroup of one launch
+  BatchRun* runs;            // device
+  int32_t* run_begin;        // device [grid + 1]: workgroup w owns runs [run_begin[w], run_begin[w+1])
+  int32_t grid;
+  int32_t nruns;
+  size_t lds;
+};
+
+struct BatchLaunch {
+  BatchTable* tables;        // device [T]
+  BatchPlan fwd, bwd;
+  int64_t dv_len;            // sum over tables of N + 1
+};
+
+hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
+                        float* dv, hipStream_t s);
+hipError_t configure_batch_kernels(int max_lds);
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s);

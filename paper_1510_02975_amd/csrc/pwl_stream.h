@@ -1,0 +1,277 @@
+// Device building blocks of the streaming evaluators (single-table and
+// batched): the LDS image of a table, the segment locate, one point of
+// Algorithm 1 and of its derivative, and one grid-stride iteration over U
+// float4 vectors per thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pwl_internal.h"
+#include "pwl_locate.h"
+
+namespace pwl {
+namespace stream {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct Smem {
+  float4* rec;      // [N]           {x_k, v_k, slope_k, 1/h_k}
+  float* knot;      // [N + pad]     knot[k] = x_k for 1 <= k <= N-1, NaN elsewhere
+  uint16_t* lo;     // [K + 1]       lo[u] = #{interior knots in cells < u}; lo[K] = N - 1
+  double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
+};
+
+__device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
+  Smem s;
+  s.rec = reinterpret_cast<float4*>(base);
+  s.knot = reinterpret_cast<float*>(s.rec + N);
+  s.lo = reinterpret_cast<uint16_t*>(s.knot + N + kKnotPad);
+  s.dv = backward ? reinterpret_cast<double*>(
+                        (reinterpret_cast<uintptr_t>(s.lo + ((K + 2) & ~1)) + 7) & ~(uintptr_t)7)
+                  : nullptr;
+  return s;
+}
+
+// Copy the table into LDS.  With v_override the vertex values come from the
+// caller and slopes are re-derived as (v_{k+1} - v_k) / h_k in FP32.  The
+// knot sentinels are NaN so that every compare against them is false, even
+// for x = +inf.
+__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo,
+                                            const Smem& s) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = tid; k < t.N; k += nt) {
+    float4 r = t.rec[k];
+    if (vo != nullptr) {
+      const float v0 = vo[k], v1 = vo[k + 1];
+      r.y = v0;
+      r.z = (v1 - v0) * r.w;
+    }
+    s.rec[k] = r;
+  }
+  const float qnan = __builtin_nanf("");
+  for (int k = tid; k < t.N + kKnotPad; k += nt)
+    s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
+  for (int u = tid; u <= t.K; u += nt) s.lo[u] = t.lo[u];
+}
+
+__device__ __forceinline__ float clamp_nan(float x, float a, float b) {
+  return (x < a) ? a : ((x > b) ? b : x);   // NaN passes through
+}
+
+// Segment of x when no map cell holds more than MAXC knots: compare x with
+// the MAXC knots that follow lo[cell(x)].  Knots beyond the cell's own are
+// greater than x (they lie in later cells) and the sentinels are NaN, so the
+// extra compares are false; the count of true compares is exact.
+template <int MAXC>
+__device__ __forceinline__ int locate_fixed(float x, const EvalTable& t, const Smem& s) {
+  const int u = map_cell(x, t.a32, t.scale32, t.K);
+  const int lo = s.lo[u];
+  int seg = lo;
+#pragma unroll
+  for (int j = 1; j <= MAXC; ++j) seg += (x >= s.knot[lo + j]) ? 1 : 0;
+  return seg;
+}
+
+// Any number of knots per cell: the count is lo[u+1] - lo[u].
+__device__ __forceinline__ int locate_any(float x, const EvalTable& t, const Smem& s) {
+  const int u = map_cell(x, t.a32, t.scale32, t.K);
+  const int lo = s.lo[u];
+  const int cnt = (int)s.lo[u + 1] - lo;
+  int seg = lo;
+  for (int j = 1; j <= cnt; ++j) seg += (x >= s.knot[lo + j]) ? 1 : 0;
+  return seg;
+}
+
+template <int MAXC>
+__device__ __forceinline__ int locate(float x, const EvalTable& t, const Smem& s) {
+  if (MAXC > 0) return locate_fixed<MAXC>(x, t, s);
+  return locate_any(x, t, s);
+}
+
+template <int MAXC>
+__device__ __forceinline__ float eval_point(float x, const EvalTable& t, const Smem& s) {
+  const int seg = locate<MAXC>(x, t, s);
+  const float4 r = s.rec[seg];
+  return fmaf(clamp_nan(x, t.a32, t.b32) - r.x, r.z, r.y);
+}
+
+template <int MAXC, bool WY, bool WDX, bool WDV>
+__device__ __forceinline__ void backward_point(float x, float g, const EvalTable& t, const Smem& s,
+                                               float& y, float& dx) {
+  const int seg = locate<MAXC>(x, t, s);
+  const float4 r = s.rec[seg];
+  const float d = clamp_nan(x, t.a32, t.b32) - r.x;
+  if (WY) y = fmaf(d, r.z, r.y);
+  if (WDX) {
+    const bool inside = (x >= t.a32) && (x <= t.b32);
+    dx = inside ? g * r.z : ((x != x) ? x : 0.0f);
+  }
+  if (WDV) {
+    if (x == x) {
+      // The workgroup's dL/dv lives in LDS as FP64: FP64 LDS atomic adds run
+      // at full rate on gfx950 (FP32 ones take a slow path) and keep the
+      // per-workgroup sums exact to FP32 output precision.  Workgroup scope,
+      // relaxed: no point has to wait for the thread's outstanding stores.
+      const float w1 = (d * r.w) * g;   // delta g
+      __hip_atomic_fetch_add(s.dv + seg, (double)(g - w1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(s.dv + seg + 1, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+}
+
+// One iteration over U float4 vectors per thread: all loads, then all table
+// lookups, then all stores.  Full iterations run unguarded so the compiler
+// can count outstanding memory operations exactly (a guarded load makes
+// every later wait a wait for all stores); the last, partial iteration of a
+// thread is guarded.
+template <int U, int MAXC, bool GUARD>
+__device__ __forceinline__ void fwd_iter(const EvalTable& t, const Smem& s, const v4f* __restrict__ x4,
+                                         v4f* __restrict__ y4, int64_t base, int64_t bs, int64_t n4) {
+  v4f xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = base + u * bs;
+    if (!GUARD || i < n4) xv[u] = __builtin_nontemporal_load(x4 + i);
+  }
+  v4f yv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    yv[u].x = eval_point<MAXC>(xv[u].x, t, s);
+    yv[u].y = eval_point<MAXC>(xv[u].y, t, s);
+    yv[u].z = eval_point<MAXC>(xv[u].z, t, s);
+    yv[u].w = eval_point<MAXC>(xv[u].w, t, s);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = base + u * bs;
+    if (!GUARD || i < n4) __builtin_nontemporal_store(yv[u], y4 + i);
+  }
+}
+
+// Which points of [begin, end) go through 16-byte vectors: the arrays share
+// their alignment phase (vec), so [head, 4 vend) is vectorised and the
+// points before `head` and from max(head, 4 vend) on are scalar.
+struct Split {
+  int64_t head, vbeg, vend;
+};
+
+__device__ __forceinline__ Split split_range(const float* p, int64_t begin, int64_t end, bool vec) {
+  Split r;
+  if (!vec) {
+    r.head = end;
+    r.vbeg = r.vend = 0;
+    return r;
+  }
+  // element index whose address is 16-byte aligned, at or after begin
+  const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(p) >> 2) & 3);
+  int64_t h = begin + ((4 - ((phase + begin) & 3)) & 3);
+  if (h > end) h = end;
+  r.head = h;
+  r.vbeg = (phase + h) >> 2;               // in units of the aligned float4 array
+  r.vend = (phase + end) >> 2;
+  if (r.vend < r.vbeg) r.vend = r.vbeg;
+  return r;
+}
+
+// Forward over points [begin, end) by `nblk` cooperating workgroups (this one
+// is number `blk`): workgroup blk streams vectors blk*bs*U + u*bs + tid of
+// each stride of nblk*bs*U vectors.
+template <int U, int MAXC>
+__device__ __forceinline__ void fwd_range(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+                                          float* __restrict__ y, int64_t begin, int64_t end, bool vec,
+                                          int64_t blk, int64_t nblk) {
+  const Split sp = split_range(x, begin, end, vec);
+  const int64_t bs = blockDim.x, tid = threadIdx.x;
+  const int64_t gtid = blk * bs + tid, gthreads = nblk * bs;
+  for (int64_t i = begin + gtid; i < sp.head; i += gthreads) y[i] = eval_point<MAXC>(x[i], t, s);
+  if (sp.vend > sp.vbeg) {
+    const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
+    const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x - phase);
+    v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y - phase);
+    const int64_t stride = nblk * bs * U;
+    int64_t base = sp.vbeg + blk * bs * U + tid;
+    for (; base + (U - 1) * bs < sp.vend; base += stride) fwd_iter<U, MAXC, false>(t, s, x4, y4, base, bs, sp.vend);
+    if (base < sp.vend) fwd_iter<U, MAXC, true>(t, s, x4, y4, base, bs, sp.vend);
+  }
+  const int64_t tail = (sp.vend > sp.vbeg) ? 4 * sp.vend - (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3)
+                                           : sp.head;
+  for (int64_t i = (tail > sp.head ? tail : sp.head) + gtid; i < end; i += gthreads)
+    y[i] = eval_point<MAXC>(x[i], t, s);
+}
+
+template <int U, bool WY, bool WDX, bool WDV>
+struct Bwd {
+  template <int MAXC, bool GUARD>
+  __device__ __forceinline__ static void iter(const EvalTable& t, const Smem& s, const v4f* __restrict__ x4,
+                                              const v4f* __restrict__ g4, v4f* __restrict__ y4,
+                                              v4f* __restrict__ dx4, int64_t base, int64_t bs, int64_t n4) {
+    v4f xv[U], gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * bs;
+      if (!GUARD || i < n4) {
+        xv[u] = __builtin_nontemporal_load(x4 + i);
+        gv[u] = __builtin_nontemporal_load(g4 + i);
+      }
+    }
+    v4f yv[U], dxv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (GUARD && base + u * bs >= n4) continue;
+      float yy = 0.0f, dd = 0.0f;
+      backward_point<MAXC, WY, WDX, WDV>(xv[u].x, gv[u].x, t, s, yy, dd); yv[u].x = yy; dxv[u].x = dd;
+      backward_point<MAXC, WY, WDX, WDV>(xv[u].y, gv[u].y, t, s, yy, dd); yv[u].y = yy; dxv[u].y = dd;
+      backward_point<MAXC, WY, WDX, WDV>(xv[u].z, gv[u].z, t, s, yy, dd); yv[u].z = yy; dxv[u].z = dd;
+      backward_point<MAXC, WY, WDX, WDV>(xv[u].w, gv[u].w, t, s, yy, dd); yv[u].w = yy; dxv[u].w = dd;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + u * bs;
+      if (!GUARD || i < n4) {
+        if (WY) __builtin_nontemporal_store(yv[u], y4 + i);
+        if (WDX) __builtin_nontemporal_store(dxv[u], dx4 + i);
+      }
+    }
+  }
+
+  // Fused forward + backward over points [begin, end), cooperating
+  // workgroups as in fwd_range.
+  template <int MAXC>
+  __device__ __forceinline__ static void range(const EvalTable& t, const Smem& s,
+                                               const float* __restrict__ x, const float* __restrict__ g,
+                                               float* __restrict__ y, float* __restrict__ dx, int64_t begin,
+                                               int64_t end, bool vec, int64_t blk, int64_t nblk) {
+    const Split sp = split_range(x, begin, end, vec);
+    const int64_t bs = blockDim.x, tid = threadIdx.x;
+    const int64_t gtid = blk * bs + tid, gthreads = nblk * bs;
+    for (int64_t i = begin + gtid; i < sp.head; i += gthreads) scalar<MAXC>(t, s, x, g, y, dx, i);
+    const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
+    if (sp.vend > sp.vbeg) {
+      const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x - phase);
+      const v4f* __restrict__ g4 = reinterpret_cast<const v4f*>(g - phase);
+      v4f* __restrict__ y4 = WY ? reinterpret_cast<v4f*>(y - phase) : nullptr;
+      v4f* __restrict__ dx4 = WDX ? reinterpret_cast<v4f*>(dx - phase) : nullptr;
+      const int64_t stride = nblk * bs * U;
+      int64_t base = sp.vbeg + blk * bs * U + tid;
+      for (; base + (U - 1) * bs < sp.vend; base += stride)
+        iter<MAXC, false>(t, s, x4, g4, y4, dx4, base, bs, sp.vend);
+      if (base < sp.vend) iter<MAXC, true>(t, s, x4, g4, y4, dx4, base, bs, sp.vend);
+    }
+    const int64_t tail = (sp.vend > sp.vbeg) ? 4 * sp.vend - phase : sp.head;
+    for (int64_t i = (tail > sp.head ? tail : sp.head) + gtid; i < end; i += gthreads)
+      scalar<MAXC>(t, s, x, g, y, dx, i);
+  }
+
+  template <int MAXC>
+  __device__ __forceinline__ static void scalar(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+                                                const float* __restrict__ g, float* __restrict__ y,
+                                                float* __restrict__ dx, int64_t i) {
+    float yy = 0.0f, dd = 0.0f;
+    backward_point<MAXC, WY, WDX, WDV>(x[i], g[i], t, s, yy, dd);
+    if (WY) y[i] = yy;
+    if (WDX) dx[i] = dd;
+  }
+};
+
+}  // namespace stream
+}  // namespace pwl

@@ -108,3 +108,41 @@ def test_binding_rejects_host_tensors():
         P.binding._ptr(torch.zeros(4), name="x")
     with pytest.raises(TypeError):
         P.binding._ptr(torch.zeros(4, dtype=torch.float64), name="x")
+
+
+def test_batch_create_rejects_invalid_arguments_on_host():
+    lib = library()
+    out = ctypes.c_void_p(5)
+    offs = (ctypes.c_int64 * 3)(0, 4, 2)
+    tabs = (ctypes.c_void_p * 2)(1, 2)
+    assert lib.pwl_batch_create(tabs, 2, offs, None, ctypes.byref(out)) == -1   # decreasing offsets
+    assert out.value is None
+    offs = (ctypes.c_int64 * 3)(1, 4, 8)
+    assert lib.pwl_batch_create(tabs, 2, offs, None, ctypes.byref(out)) == -1   # offsets[0] != 0
+    offs = (ctypes.c_int64 * 3)(0, 4, 8)
+    assert lib.pwl_batch_create(tabs, 0, offs, None, ctypes.byref(out)) == -1   # T < 1
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.pwl_batch_create(nulls, 2, offs, None, ctypes.byref(out)) == -1  # NULL table
+    assert lib.pwl_batch_create(tabs, 2, offs, None, None) == -1
+    assert lib.pwl_batch_eval(None, None, None, None) == -1
+    assert lib.pwl_batch_eval_backward(None, None, None, None, None, None, None) == -1
+    assert lib.pwl_batch_replay(None, None) == -1
+    assert lib.pwl_batch_info(None, None, None, None, None, None, None, None) == -1
+    lib.pwl_batch_free(None)
+
+
+def test_set_launch_validation():
+    lib = library()
+    assert lib.pwl_set_launch(0, 3, 256, 2) == -1
+    assert lib.pwl_set_launch(0, 2, 100, 2) == -1
+    assert lib.pwl_set_launch(0, 2, 256, 0) == -1
+    assert lib.pwl_set_launch(7, 2, 256, 2) == -1
+    u, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.pwl_get_launch(0, ctypes.byref(u), ctypes.byref(b), ctypes.byref(w)) == 0
+    assert lib.pwl_set_launch(0, 1, 128, 3) == 0
+    u2 = ctypes.c_int32()
+    lib.pwl_get_launch(0, ctypes.byref(u2), None, None)
+    assert u2.value == 1
+    assert lib.pwl_set_launch(0, 0, 0, 0) == 0            # defaults back
+    lib.pwl_get_launch(0, ctypes.byref(u2), None, None)
+    assert u2.value == u.value

@@ -1,0 +1,142 @@
+"""Batched multi-table evaluation (one persistent launch) against per-table
+launches and the FP64 oracle, and its captured HIP graph replayed several
+times with the program's own work in between."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _tables(P, T=40, seed=7, max_n=4096):
+    """Mixed tables (the many-table recipe at a small total) plus the points."""
+    specs = W.many_tables(T=T, total_points=1 << 21, seed=seed)
+    rng = np.random.default_rng(seed)
+    for k, s in enumerate(specs):
+        s["N"] = int(min(s["N"], max_n))
+        if k % 9 == 4:
+            s["n"] = 0                    # empty tables
+        elif k % 7 == 3:
+            s["n"] = int(rng.integers(1, 6))   # a handful of points, odd offsets
+    tabs = [P.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"])
+            for s in specs]
+    x, offs = W.many_tables_points(specs, seed=0)
+    return specs, tabs, x, offs
+
+
+def test_batch_forward_matches_per_table_and_oracle():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    specs, tabs, x, offs = _tables(P)
+    say("batch forward: %d tables, %d points" % (len(tabs), len(x)))
+    xt = torch.from_numpy(x).to(dev)
+    bt = P.pwl_batch_create(tabs, offs)
+    assert bt.npoints == len(x) and bt.T == len(tabs)
+    y = P.pwl_batch_eval(bt, xt).cpu().numpy()
+    for t, s, o0, o1 in zip(tabs, specs, offs[:-1], offs[1:]):
+        if o1 == o0:
+            continue
+        y1 = P.pwl_eval(t, xt[o0:o1]).cpu().numpy()
+        assert np.array_equal(y[o0:o1], y1)          # same kernel body, bit for bit
+        d = P.pwl_table_download(t)
+        yr = O.evaluate(d["knots"].astype(np.float64), d["values"].astype(np.float64),
+                        x[o0:o1].astype(np.float64))
+        assert np.max(np.abs(y[o0:o1] - yr)) <= Y_TOL * fmax_abs(s["func"], s["params"], s["a"], s["b"])
+    bt.free()
+
+
+def test_batch_backward_matches_per_table():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    specs, tabs, x, offs = _tables(P, T=25, seed=3)
+    g = W.upstream_grad(len(x), 5)
+    xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
+    bt = P.pwl_batch_create(tabs, offs)
+    y, dx, dv = P.pwl_batch_eval_backward(bt, xt, gt)
+    y, dx, dv = y.cpu().numpy(), dx.cpu().numpy(), dv.cpu().numpy()
+    for i, (t, o0, o1) in enumerate(zip(tabs, offs[:-1], offs[1:])):
+        d0, d1 = bt.dv_offsets[i], bt.dv_offsets[i + 1]
+        if o1 == o0:
+            assert np.all(dv[d0:d1] == 0.0)
+            continue
+        y1, dx1, dv1 = P.pwl_eval_backward(t, xt[o0:o1], gt[o0:o1])
+        assert np.array_equal(y[o0:o1], y1.cpu().numpy())
+        assert np.array_equal(dx[o0:o1], dx1.cpu().numpy())
+        d = P.pwl_table_download(t)
+        X = d["knots"].astype(np.float64)
+        _, _, dvr = O.evaluate_backward(X, d["values"].astype(np.float64), x[o0:o1].astype(np.float64),
+                                        g[o0:o1].astype(np.float64))
+        _, _, wk = O.evaluate_backward(X, np.zeros(len(X)), x[o0:o1].astype(np.float64),
+                                       np.abs(g[o0:o1]).astype(np.float64))
+        assert np.all(np.abs(dv[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30)
+    # without y and dx
+    _, _, dv2 = P.pwl_batch_eval_backward(bt, xt, gt, want=())
+    assert np.allclose(dv2.cpu().numpy(), dv, rtol=1e-5, atol=1e-5)
+    bt.free()
+
+
+def test_batch_graph_replays_match_eager():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    specs, tabs, x, offs = _tables(P, T=30, seed=11)
+    g = W.upstream_grad(len(x), 2)
+    xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
+    bt = P.pwl_batch_create(tabs, offs)
+    y_e = P.pwl_batch_eval(bt, xt).clone()
+    ye, dxe, dve = P.pwl_batch_eval_backward(bt, xt, gt)
+    ye, dxe, dve = ye.clone(), dxe.clone(), dve.clone()
+    y = torch.full_like(xt, 7.0)
+    P.pwl_batch_capture(bt, xt, y)
+    for rep in range(4):
+        y.fill_(float(rep))                    # eager work between replays
+        torch.cuda.synchronize()
+        P.pwl_batch_replay(bt)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_e), rep
+    yb, dxb = torch.empty_like(xt), torch.empty_like(xt)
+    dvb = torch.full((bt.dv_len,), 3.0, device=dev)
+    P.pwl_batch_capture(bt, xt, yb, g=gt, dx=dxb, dv=dvb)
+    for rep in range(4):
+        dvb.fill_(float(rep + 1))              # the graph must clear dv itself
+        yb.zero_()
+        torch.cuda.synchronize()
+        P.pwl_batch_replay(bt)
+        torch.cuda.synchronize()
+        assert torch.equal(yb, ye) and torch.equal(dxb, dxe), rep
+        assert torch.allclose(dvb, dve, rtol=1e-5, atol=1e-4), rep
+    bt.free()
+
+
+def test_batch_misaligned_and_degenerate_shapes():
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    t = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 300, O.OPTIMAL, O.PROJ)
+    u = P.pwl_build(O.BESSEL_J0, (1.0,), 0.0, 50.0, 40, O.UNIFORM, O.INTERP)
+    base = torch.from_numpy(W.uniform_points(-6.0, 51.0, 20011, 9)).to(dev)
+    for off in (0, 1, 2, 3):
+        x = base[off:off + 20003]
+        offs = [0, 7, 7, 12345, 20003]
+        bt = P.pwl_batch_create([t, u, t, u], offs)
+        y = torch.empty(20006, device=dev)[off % 3:off % 3 + 20003]
+        P.pwl_batch_eval(bt, x, y)
+        ref = torch.cat([P.pwl_eval(t, x[0:7]), P.pwl_eval(t, x[7:12345]), P.pwl_eval(u, x[12345:20003])])
+        assert torch.equal(y, ref), off
+        bt.free()
+    # a single table equals pwl_eval; zero points is valid
+    bt = P.pwl_batch_create([t], [0, 20011])
+    assert torch.equal(P.pwl_batch_eval(bt, base), P.pwl_eval(t, base))
+    bt.free()
+    bt = P.pwl_batch_create([t, u], [0, 0, 0])
+    P.pwl_batch_eval(bt, base[:0], base[:0].clone())
+    _, _, dv = P.pwl_batch_eval_backward(bt, base[:0], base[:0], want=())
+    assert torch.all(dv == 0.0) and dv.numel() == 301 + 41
+    bt.free()
