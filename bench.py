@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 FWD_BYTES_PER_POINT = 8      # x in, y out (FP32)
 FUSED_BYTES_PER_POINT = 16   # x, g in; y, dx out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_eval_fwd_gauss_n1024.json")
-KERNEL_SOURCES = ["paper_1510_02975_amd/csrc/pwl_eval.hip", "paper_1510_02975_amd/csrc/pwl_locate.h",
-                  "paper_1510_02975_amd/csrc/pwl_internal.h"]
+KERNEL_SOURCES = ["paper_1510_02975_amd/csrc/pwl_eval.hip", "paper_1510_02975_amd/csrc/pwl_stream.h",
+                  "paper_1510_02975_amd/csrc/pwl_locate.h", "paper_1510_02975_amd/csrc/pwl_internal.h"]
 
 
 def log(msg):

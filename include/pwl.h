@@ -205,9 +205,9 @@ pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream)
 
 /*
  * pwl_batch_eval_backward - fused forward + backward for every table: y and
- * dx (each nullable) as in pwl_eval_backward; dv (required) is the
- * concatenation of every table's N_t + 1 gradients, table t first, and is
- * OVERWRITTEN.
+ * dx (each nullable) as in pwl_eval_backward; g is required unless the
+ * batch has no points; dv (required) is the concatenation of every table's
+ * N_t + 1 gradients, table t first, and is OVERWRITTEN.
  */
 pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g, float* y, float* dx,
                                    float* dv, void* stream);

@@ -220,8 +220,6 @@ size_t layout(pwl::TableDev* td, char* base, int N, int K, int G) {
   td->values64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
   td->status = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4));
   td->totals = reinterpret_cast<double*>(take(sizeof(double) * G));
-  td->quad_l = reinterpret_cast<float*>(take(sizeof(float) * N));
-  td->quad_r = reinterpret_cast<float*>(take(sizeof(float) * N));
   td->ucell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (N + 1)));
   return off;
 }
@@ -560,10 +558,13 @@ pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g
                                    void* stream) {
   pwl_status st = check_batch(bt);
   if (st != PWL_OK) return st;
-  if (g == nullptr) return fail(PWL_EINVAL, "g must be non-NULL");
-  st = check_batch_args(bt, x, g, y, dx, dv);
+  if (g == nullptr && bt->npoints > 0) return fail(PWL_EINVAL, "g must be non-NULL");
+  if (dv == nullptr) return fail(PWL_EINVAL, "the batched backward needs dv");
+  // With no points g is never read; any non-NULL stand-in selects the backward.
+  const float* gg = (g != nullptr) ? g : dv;
+  st = check_batch_args(bt, x, gg, y, dx, dv);
   if (st != PWL_OK) return st;
-  PWL_HIP(pwl::launch_batch(bt->bl, x, g, y, dx, dv, static_cast<hipStream_t>(stream)));
+  PWL_HIP(pwl::launch_batch(bt->bl, x, gg, y, dx, dv, static_cast<hipStream_t>(stream)));
   return PWL_OK;
 }
 

@@ -4,14 +4,13 @@
 //     k_density_totals   FP64 |f''|^(2/5) on the fine grid, trapezoid sum per workgroup
 //     k_invert_knots     FP64 prefix of those sums, targets i S_M / N, linear inversion;
 //                        per knot also its map cell and, for the interpolant, f(x_i)
-//   uniform partition (Sec. IV): k_uniform_knots writes the knots, cells and values
 //   every table:
-//     k_segments         per segment: its cells of the uniform index map, the
-//                        knot-collapse check, the deepest cell; for the projection
-//                        (Sec. II-B2) FP32 Gauss-Legendre integrals of f against both
-//                        hats, one lane per (segment, node)
-//     k_finalize         one workgroup: the FP64 solve of M c = b (parallel cyclic
-//                        reduction) and the packed records {x_k, v_k, slope_k, 1/h_k}
+//     k_finalize         one workgroup: uniform knots (Sec. IV) when asked, the
+//                        uniform index map, the knot-collapse check, for the
+//                        projection (Sec. II-B2) FP32 Gauss-Legendre integrals of f
+//                        against the hats and the FP64 solve of M c = b (parallel
+//                        cyclic reduction), and the packed records
+//                        {x_k, v_k, slope_k, 1/h_k}
 #include <hip/hip_runtime.h>
 
 #include "pwl_func.h"
@@ -191,95 +190,87 @@ __global__ __launch_bounds__(kScanThreads) void k_invert_knots(BuildParams bp, T
   }
 }
 
-// Uniform partition: knots, cells and interpolant values.
-__global__ __launch_bounds__(kBuildThreads) void k_uniform_knots(BuildParams bp, TableDev td) {
-  const int k = blockIdx.x * kBuildThreads + threadIdx.x;
-  if (k <= bp.N) emit_knot(bp, td, k, uniform_knot(bp, k));
-  if (k == 0) {
-    td.status[0] = 0u;
-    td.status[1] = 0u;
-  }
-}
-
-// Per segment k (between knots k and k+1), once the knots are known:
-//  - the uniform index map lo[u] = #{interior knots with cell < u}: segment k
-//    owns the cells (cell(x_k), cell(x_{k+1})], with cell(x_0) = -1 and
-//    cell(x_N) = K - 1, so every cell is written exactly once when the knots
-//    increase (k_finalize clears the map of a collapsed table);
-//  - the knot-collapse check x_{k+1} > x_k;
-//  - the longest run of interior knots sharing one cell (the evaluator's
-//    unrolled compare depth);
-//  - for the projection, <f, phi_k> pieces by Gauss-Legendre: lane q of a
-//    16-lane group evaluates node q and the group reduces its (1 - t) f and
-//    t f products with cross-lane shuffles.
-template <int LANES>
-__global__ __launch_bounds__(kBuildThreads) void k_segments(BuildParams bp, TableDev td) {
-  const int gid = blockIdx.x * kBuildThreads + threadIdx.x;
-  const int k = gid / LANES;
-  const int q = gid % LANES;
-  int run = 0;
-  if (k < bp.N && q == 0) {
-    const int u0 = (k == 0) ? -1 : td.ucell[k];
-    const int u1 = (k + 1 == bp.N) ? bp.K - 1 : td.ucell[k + 1];
-    for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
-    if (!(td.knots[k + 1] > td.knots[k])) atomicOr(td.status, (uint32_t)PWL_FLAG_KNOTS_COLLAPSED);
-    if (k >= 1 && (k == 1 || td.ucell[k - 1] != u0)) {   // first interior knot of its cell
-      run = 1;
-      while (k + run <= bp.N - 1 && td.ucell[k + run] == u0) ++run;
-    }
-  }
-  if (k == 0 && q == 0) td.lo[bp.K] = (uint16_t)(bp.N - 1);
-  // one atomic per wavefront for the deepest cell
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) run = max(run, __shfl_xor(run, m));
-  if ((threadIdx.x & 63) == 0 && run > 0) atomicMax(td.status + 1, (uint32_t)run);
-  if (LANES == 1) return;
-  float sl = 0.0f, sr = 0.0f, h = 0.0f;
-  if (k < bp.N) {
-    const float xk = td.knots[k];
-    h = td.knots[k + 1] - xk;
-    const float t = bp.gl.t[q];
-    const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
-    sl = (1.0f - t) * fq;
-    sr = t * fq;
-  }
-#pragma unroll
-  for (int m = LANES / 2; m >= 1; m >>= 1) {
-    sl += __shfl_xor(sl, m, LANES);
-    sr += __shfl_xor(sr, m, LANES);
-  }
-  if (k < bp.N && q == 0) {
-    td.quad_l[k] = h * sl;
-    td.quad_r[k] = h * sr;
-  }
-}
-
 constexpr int kFinalizeThreads = 1024;
 constexpr int kRowsPerThread = (PWL_MAX_N + 1 + kFinalizeThreads - 1) / kFinalizeThreads;
 
+// Everything after the knots, in one workgroup:
+//  1. (uniform partition) the knots x_k = a + (b - a) k / N, their cells and
+//     interpolant values;
+//  2. per segment k: its cells of the uniform index map lo[u] = #{interior
+//     knots with cell < u} - segment k owns (cell(x_k), cell(x_{k+1})], with
+//     cell(x_0) = -1 and cell(x_N) = K - 1, so each cell is written once when
+//     the knots increase; the knot-collapse check; the deepest cell (the
+//     evaluator's unrolled compare depth);
+//  3. (projection) <f, phi_k> by 16-point Gauss-Legendre per segment, one lane
+//     per (segment, node), reduced across each 16-lane group;
+//  4. (projection) the FP64 solve of M c = b by parallel cyclic reduction;
+//  5. the packed records {x_k, v_k, slope_k, 1/h_k} (NaN for a collapsed
+//     table, whose map is then cleared).
 __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, TableDev td) {
   extern __shared__ double s_pcr[];
   const int N = bp.N, n = N + 1;
   const int tid = threadIdx.x;
   double* A = s_pcr;
-  double* B = A + n;
-  double* Cu = B + n;
+  double* R = A + n;      // reciprocal diagonal during the solve
+  double* Cu = R + n;
   double* D = Cu + n;
-  const bool collapsed = (td.status[0] & PWL_FLAG_KNOTS_COLLAPSED) != 0u;
-  if (collapsed) {
-    // The evaluators never leave the table through an all-zero map; the
-    // records below are NaN.
-    for (int u = tid; u < bp.K; u += kFinalizeThreads) td.lo[u] = 0;
+  __shared__ int s_collapsed, s_maxc;
+  if (tid == 0) {
+    s_collapsed = 0;
+    s_maxc = 0;
   }
+  if (bp.partition == PWL_UNIFORM)
+    for (int k = tid; k <= N; k += kFinalizeThreads) emit_knot(bp, td, k, uniform_knot(bp, k));
+  __syncthreads();
 
-  // 3. vertex values
+  // 2. map, collapse check, deepest cell
+  int run = 0, bad = 0;
+  for (int k = tid; k < N; k += kFinalizeThreads) {
+    const int u0 = (k == 0) ? -1 : td.ucell[k];
+    const int u1 = (k + 1 == N) ? bp.K - 1 : td.ucell[k + 1];
+    for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
+    if (!(td.knots[k + 1] > td.knots[k])) bad = 1;
+    if (k >= 1 && (k == 1 || td.ucell[k - 1] != u0)) {   // first interior knot of its cell
+      int r = 1;
+      while (k + r <= N - 1 && td.ucell[k + r] == u0) ++r;
+      run = max(run, r);
+    }
+  }
+  if (tid == 0) td.lo[bp.K] = (uint16_t)(N - 1);
+  if (bad) atomicOr(&s_collapsed, 1);
+  if (run > 0) atomicMax(&s_maxc, run);
+
+  // 3-4. vertex values
   if (bp.values == PWL_PROJ) {
+    // lane (k, q): node q of segment k; L_k goes to D[k], R_k to A[k+1]
+    for (int base = 0; base < kGaussPoints * N; base += kFinalizeThreads) {
+      const int gid = base + tid;
+      const int k = gid / kGaussPoints, q = gid % kGaussPoints;
+      float sl = 0.0f, sr = 0.0f, h = 0.0f;
+      if (k < N) {
+        const float xk = td.knots[k];
+        h = td.knots[k + 1] - xk;
+        const float t = bp.gl.t[q];
+        const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
+        sl = (1.0f - t) * fq;
+        sr = t * fq;
+      }
+#pragma unroll
+      for (int m = kGaussPoints / 2; m >= 1; m >>= 1) {
+        sl += __shfl_xor(sl, m, kGaussPoints);
+        sr += __shfl_xor(sr, m, kGaussPoints);
+      }
+      if (k < N && q == 0) {
+        D[k] = (double)(h * sl);
+        A[k + 1] = (double)(h * sr);
+      }
+    }
+    __syncthreads();
     // Gram matrix of the hat basis from the element matrix (h/6)[[2,1],[1,2]]
     // (half hats at both ends), right-hand side b_k = <f, phi_k>.  Row i is
     // owned by thread i mod 1024 for the whole solve: it keeps its diagonal
     // in registers and publishes the reciprocal for its neighbours.
     double diag[kRowsPerThread];
-    double* R = B;   // 1 / diagonal, shared
 #pragma unroll
     for (int r = 0; r < kRowsPerThread; ++r) {
       const int i = tid + r * kFinalizeThreads;
@@ -287,11 +278,13 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
       const double xi = (double)td.knots[i];
       const double hl = (i > 0) ? xi - (double)td.knots[i - 1] : 0.0;
       const double hr = (i < N) ? (double)td.knots[i + 1] - xi : 0.0;
+      const double bl = (i > 0) ? A[i] : 0.0;
+      const double br = (i < N) ? D[i] : 0.0;
+      D[i] = bl + br;
       A[i] = hl / 6.0;
       Cu[i] = hr / 6.0;
       diag[r] = hl / 3.0 + hr / 3.0;
       R[i] = 1.0 / diag[r];
-      D[i] = ((i > 0) ? (double)td.quad_r[i - 1] : 0.0) + ((i < N) ? (double)td.quad_l[i] : 0.0);
     }
     __syncthreads();
     // Parallel cyclic reduction: at stride s every row eliminates its
@@ -340,7 +333,10 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   }
   __syncthreads();
 
-  // 4. values, flags and packed records
+  // 5. values, flags and packed records
+  const bool collapsed = s_collapsed != 0;
+  if (collapsed)   // the evaluators never leave the table through an all-zero map
+    for (int u = tid; u < bp.K; u += kFinalizeThreads) td.lo[u] = 0;
   for (int i = tid; i < n; i += kFinalizeThreads) {
     const double c = D[i];
     td.values64[i] = c;
@@ -361,6 +357,13 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     }
     td.rec[k] = r;
   }
+  if (tid == 0) {
+    // the density kernels may have raised DEGENERATE / NONFINITE
+    uint32_t st = (bp.partition == PWL_OPTIMAL) ? td.status[0] : 0u;
+    if (collapsed) st |= PWL_FLAG_KNOTS_COLLAPSED;
+    td.status[0] = st;
+    td.status[1] = (uint32_t)s_maxc;
+  }
 }
 
 }  // namespace
@@ -369,16 +372,6 @@ hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s
   if (bp.partition == PWL_OPTIMAL) {
     hipLaunchKernelGGL(k_density_totals, dim3(bp.G), dim3(kScanThreads), 0, s, bp, td);
     hipLaunchKernelGGL(k_invert_knots, dim3(bp.G), dim3(kScanThreads), 0, s, bp, td);
-  } else {
-    const int nb = (bp.N + 1 + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_uniform_knots, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
-  }
-  if (bp.values == PWL_PROJ) {
-    const int nb = (bp.N * kGaussPoints + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_segments<kGaussPoints>, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
-  } else {
-    const int nb = (bp.N + kBuildThreads - 1) / kBuildThreads;
-    hipLaunchKernelGGL(k_segments<1>, dim3(nb), dim3(kBuildThreads), 0, s, bp, td);
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), finalize_lds_bytes(bp.N), s, bp, td);
   return hipGetLastError();

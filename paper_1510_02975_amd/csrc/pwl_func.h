@@ -68,9 +68,10 @@ __device__ inline double f_second64(const FuncDesc& f, double x) {
   }
 }
 
-// Local knot density |f''|^(2/5) (Sec. III-B1).
+// Local knot density |f''|^(2/5) (Sec. III-B1), as 2^(0.4 log2 |f''|)
+// (0 at a zero of f'').
 __device__ inline double knot_density(const FuncDesc& f, double x) {
-  return pow(fabs(f_second64(f, x)), 0.4);
+  return exp2(0.4 * log2(fabs(f_second64(f, x))));
 }
 
 }  // namespace pwl

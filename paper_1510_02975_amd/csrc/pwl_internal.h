@@ -37,8 +37,6 @@ struct TableDev {
   uint32_t* status;   // [0] build flags (PWL_FLAG_*), [1] most knots in one map cell
   // build scratch
   double* totals;     // [G] per-workgroup density sums
-  float* quad_l;      // [N] integral of f (1 - t) h over segment k   (-> b_k)
-  float* quad_r;      // [N] integral of f t h over segment k         (-> b_{k+1})
   int32_t* ucell;     // [N+1] map cell of every knot
 };
 

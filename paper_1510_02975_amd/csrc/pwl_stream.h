@@ -112,8 +112,14 @@ __device__ __forceinline__ void backward_point(float x, float g, const EvalTable
       // at full rate on gfx950 (FP32 ones take a slow path) and keep the
       // per-workgroup sums exact to FP32 output precision.  Workgroup scope,
       // relaxed: no point has to wait for the thread's outstanding stores.
-      const float w1 = (d * r.w) * g;   // delta g
-      __hip_atomic_fetch_add(s.dv + seg, (double)(g - w1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // Each hat weight comes from its own knot distance, (x_{i+1} - x)/h and
+      // (x - x_i)/h: forming (1 - delta) g as g - delta g would cancel when
+      // delta is near 1.
+      const float xc = clamp_nan(x, t.a32, t.b32);
+      const float x1 = (seg + 1 < t.N) ? s.knot[seg + 1] : t.b32;
+      const float w0 = ((x1 - xc) * r.w) * g;   // (1 - delta) g
+      const float w1 = (d * r.w) * g;           // delta g
+      __hip_atomic_fetch_add(s.dv + seg, (double)w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __hip_atomic_fetch_add(s.dv + seg + 1, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
