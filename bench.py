@@ -150,68 +150,37 @@ def ingest_pmc(fetch_dir, write_dir, command, n_points):
 
 
 def ingest_trace(trace_dir, out_md, command):
-    """Text summary of a rocprofv3 --kernel-trace --stats run."""
+    """Text summary of a rocprofv3 --kernel-trace --stats run: the tool's
+    per-kernel statistics, then per (kernel, grid, workgroup) launch shape
+    from the dispatch trace, which separates the headline launches from the
+    small per-table ones of the same kernel."""
     rows = _kernel_rows(_find(trace_dir, "kernel_stats.csv"))
+
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "")
+        return name.split("(")[0] if "(" in name else name
     lines = ["# rocprofv3 kernel statistics", "", "Command (from the repository root):", "",
-             "    " + command, "",
+             "    " + command, "", "## Per kernel (rocprofv3 --stats)", "",
              "| kernel | calls | average us | min us | max us | share |",
              "|---|---|---|---|---|---|"]
     for r in rows:
-        name = r["Name"].replace("(anonymous namespace)::", "")
-        name = name.split("(")[0] if "(" in name else name
         lines.append("| %s | %s | %.2f | %.2f | %.2f | %.1f%% |" % (
-            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    trace = _kernel_rows(_find(trace_dir, "kernel_trace.csv"))
+    groups = {}
+    for r in trace:
+        key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines += ["", "## Per launch shape (dispatch trace; grid in threads)", "",
+              "| kernel | grid | workgroup | calls | average us | median us | min us | max us |",
+              "|---|---|---|---|---|---|---|---|"]
+    for (name, grid, wg), d in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
+        lines.append("| %s | %d | %d | %d | %.2f | %.2f | %.2f | %.2f |" % (
+            name, grid, wg, len(d), float(np.mean(d)), float(np.median(d)), min(d), max(d)))
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
-
-
-def batch_extra(torch, P, W, dev, args):
-    """Many-table workload: 4096 tables of uneven N and uneven point counts
-    (about 2^28 points in total), one persistent launch (eager and replayed
-    from its captured graph), the fused forward+backward, and the same
-    forward as one pwl_eval launch per table."""
-    log("batch: building 4096 tables")
-    specs = W.many_tables(T=4096, total_points=1 << args.batch_log2n, seed=2)
-    tabs = [P.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"],
-                        check=False) for s in specs]
-    for t in tabs:
-        P.pwl_table_check(t)
-    x_h, offs = W.many_tables_points(specs, seed=0)
-    n = int(offs[-1])
-    log("batch: %d points" % n)
-    x = torch.from_numpy(x_h).to(dev)
-    del x_h
-    y = torch.empty_like(x)
-    bt = P.pwl_batch_create(tabs, offs)
-    t_fwd = timed_median(torch, lambda i: P.pwl_batch_eval(bt, x, y), reps=10)
-    P.pwl_batch_capture(bt, x, y)
-    t_graph = timed_median(torch, lambda i: P.pwl_batch_replay(bt), reps=10)
-    g = torch.from_numpy(W.upstream_grad(n, 1)).to(dev)
-    dx = torch.empty_like(x)
-    dv = torch.empty(bt.dv_len, dtype=torch.float32, device=dev)
-    t_fb = timed_median(torch, lambda i: P.pwl_batch_eval_backward(bt, x, g, y, dx, dv), reps=10)
-    o = [int(v) for v in offs]
-    views = [(t, x[o[k]:o[k + 1]], y[o[k]:o[k + 1]]) for k, t in enumerate(tabs) if o[k + 1] > o[k]]
-
-    def per_table(i):
-        for t, xs, ys in views:
-            P.pwl_eval(t, xs, ys)
-    t_per = timed_median(torch, per_table, reps=3, warm=1)
-    table_bytes = sum(28 * s["N"] for s in specs)
-    bt.free()
-    for t in tabs:
-        t.free()
-    return {"batch_workload": "4096 tables (Gaussian/Lorentzian/J0, N log-uniform 16..4096), %d points" % n,
-            "batch_fwd_gpoints_s": n / t_fwd / 1e9,
-            "batch_fwd_hbm_frac": FWD_BYTES_PER_POINT * n / t_fwd / 1e9 / HBM_PEAK_GBS,
-            "batch_fwd_graph_gpoints_s": n / t_graph / 1e9,
-            "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9,
-            "batch_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * n / t_fb / 1e9 / HBM_PEAK_GBS,
-            "batch_per_table_launches_gpoints_s": n / t_per / 1e9,
-            "batch_grid_fwd": bt.grid_fwd, "batch_runs_fwd": bt.runs_fwd,
-            "batch_table_bytes": table_bytes}
 
 
 def main():
