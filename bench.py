@@ -9,9 +9,10 @@ then all 2^28 points are evaluated.  Input/output buffers rotate over three
 sets so no step reads the previous step's cache residue.
 
 Prints one JSON line.  Secondary figures ride along in "extra": the fused
-forward+backward on the gradient workload, direct expf, copy bandwidth, and
-the many-table workload (one batched launch, its graph replay, the fused
-backward, and one launch per table).
+forward+backward on the gradient workload, direct expf, copy bandwidth, the
+Lorentzian and J0 tables at N = 256, 1024, 4096, and the many-table workload
+(one batched launch, its graph replay, the fused backward, and one launch per
+table).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 """
@@ -183,6 +184,75 @@ def ingest_trace(trace_dir, out_md, command):
     print("\n".join(lines))
 
 
+def batch_extra(torch, P, W, dev, args):
+    """Many-table workload: 4096 tables of uneven N and uneven point counts
+    (about 2^28 points in total), one persistent launch (eager and replayed
+    from its captured graph), the fused forward+backward, and the same
+    forward as one pwl_eval launch per table."""
+    log("batch: building 4096 tables")
+    specs = W.many_tables(T=4096, total_points=1 << args.batch_log2n, seed=2)
+    tabs = [P.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"],
+                        check=False) for s in specs]
+    for t in tabs:
+        P.pwl_table_check(t)
+    x_h, offs = W.many_tables_points(specs, seed=0)
+    n = int(offs[-1])
+    log("batch: %d points" % n)
+    x = torch.from_numpy(x_h).to(dev)
+    del x_h
+    y = torch.empty_like(x)
+    bt = P.pwl_batch_create(tabs, offs)
+    t_fwd = timed_median(torch, lambda i: P.pwl_batch_eval(bt, x, y), reps=10)
+    P.pwl_batch_capture(bt, x, y)
+    t_graph = timed_median(torch, lambda i: P.pwl_batch_replay(bt), reps=10)
+    g = torch.from_numpy(W.upstream_grad(n, 1)).to(dev)
+    dx = torch.empty_like(x)
+    dv = torch.empty(bt.dv_len, dtype=torch.float32, device=dev)
+    t_fb = timed_median(torch, lambda i: P.pwl_batch_eval_backward(bt, x, g, y, dx, dv), reps=10)
+    o = [int(v) for v in offs]
+    views = [(t, x[o[k]:o[k + 1]], y[o[k]:o[k + 1]]) for k, t in enumerate(tabs) if o[k + 1] > o[k]]
+
+    def per_table(i):
+        for t, xs, ys in views:
+            P.pwl_eval(t, xs, ys)
+    t_per = timed_median(torch, per_table, reps=3, warm=1)
+    table_bytes = sum(28 * s["N"] for s in specs)
+    bt.free()
+    for t in tabs:
+        t.free()
+    return {"batch_workload": "4096 tables (Gaussian/Lorentzian/J0, N log-uniform 16..4096), %d points" % n,
+            "batch_fwd_gpoints_s": n / t_fwd / 1e9,
+            "batch_fwd_hbm_frac": FWD_BYTES_PER_POINT * n / t_fwd / 1e9 / HBM_PEAK_GBS,
+            "batch_fwd_graph_gpoints_s": n / t_graph / 1e9,
+            "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9,
+            "batch_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * n / t_fb / 1e9 / HBM_PEAK_GBS,
+            "batch_per_table_launches_gpoints_s": n / t_per / 1e9,
+            "batch_grid_fwd": bt.grid_fwd, "batch_runs_fwd": bt.runs_fwd,
+            "batch_table_bytes": table_bytes}
+
+
+def c3_extra(torch, P, W, dev):
+    """Lorentzian on [-20, 20] and J0 on [0, 50], optimal partition, N in
+    {256, 1024, 4096}, projection values, 2^27 uniform points: forward
+    throughput per table size (the LDS footprint grows with N)."""
+    out = {}
+    for spec in (W.LORENTZ, W.BESSEL):
+        n = spec["n"]
+        x_h = W.uniform_points(spec["a"], spec["b"], n, 0)
+        xs = [torch.from_numpy(x_h).to(dev) for _ in range(2)]
+        del x_h
+        ys = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(2)]
+        for N in (256, 1024, 4096):
+            t = P.pwl_build(spec["func"], spec["params"], spec["a"], spec["b"], N, spec["partition"], W.PROJ)
+            s = timed_median(torch, lambda i: P.pwl_eval(t, xs[i % 2], ys[i % 2]))
+            key = "%s_n%d" % (spec["name"].split("_")[0], N)
+            out[key + "_gpoints_s"] = n / s / 1e9
+            out[key + "_hbm_frac"] = FWD_BYTES_PER_POINT * n / s / 1e9 / HBM_PEAK_GBS
+            t.free()
+        del xs, ys
+    return out
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--ingest-pmc":
         # --ingest-pmc FETCH_DIR WRITE_DIR LOG2N "command"
@@ -241,22 +311,24 @@ def main():
     torch.cuda.synchronize()
 
     log("timing %d steps" % args.steps)
-    ev_build = event_pairs(torch, args.steps)
-    ev_eval = event_pairs(torch, args.steps)
+    # one event between the build and the evaluation of a step and one after
+    # the evaluation (which also starts the next step's build)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks[0].record()
     for i in range(args.steps):
-        ev_build[i][0].record()
         rebuild()
-        ev_build[i][1].record()
-        ev_eval[i][0].record()
+        marks[2 * i + 1].record()
         P.pwl_eval(table, xs[i % sets], ys[i % sets])
-        ev_eval[i][1].record()
+        marks[2 * i + 2].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    eval_s = float(np.mean([s.elapsed_time(e) for s, e in ev_eval])) * 1e-3
-    build_s = float(np.mean([s.elapsed_time(e) for s, e in ev_build])) * 1e-3
+    eval_s = float(np.mean([marks[2 * i + 1].elapsed_time(marks[2 * i + 2])
+                            for i in range(args.steps)])) * 1e-3
+    build_s = float(np.mean([marks[2 * i].elapsed_time(marks[2 * i + 1])
+                             for i in range(args.steps)])) * 1e-3
     value = n * args.steps / wall / 1e9
     achieved = FWD_BYTES_PER_POINT * n / eval_s / 1e9
     log("step %.3f ms, eval kernel %.1f us (%.0f GB/s), build %.1f us"
@@ -291,6 +363,8 @@ def main():
         extra["fwd_bwd_hbm_frac"] = FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS
         del xg, gg, yg, dxg
         tg.free()
+        log("extras: Lorentzian and J0 tables, 2^27 points")
+        extra.update(c3_extra(torch, P, W, dev))
         if not args.no_batch:
             extra.update(batch_extra(torch, P, W, dev, args))
 

@@ -184,17 +184,19 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
 /* ---- batches of tables ------------------------------------------------- */
 
 /*
- * pwl_batch_create - prepare one launch that evaluates T tables, table t on
+ * pwl_batch_create - prepare the launches that evaluate T tables, table t on
  * the points [offsets[t], offsets[t+1]) of concatenated point arrays.
  *   tables[T]    tables on the current device; the batch keeps their device
  *                addresses and shapes, so free (or rebuild) a table only
  *                after freeing the batches that use it.
  *   offsets[T+1] HOST array, offsets[0] = 0, non-decreasing (empty tables
  *                allowed); offsets[T] is the total number of points.
- * The points are cut into one equal, contiguous chunk per workgroup of a
- * persistent grid (its size follows the PWL_KERNEL_BATCH launch shape at
- * creation time); each workgroup walks the table runs of its chunk and
- * re-stages its LDS copy of the table only when the table changes.
+ * Tables are split into at most two classes by LDS footprint: those that
+ * fit the PWL_KERNEL_BATCH launch shape's workgroups per CU (at creation
+ * time), and the larger ones, which run with fewer workgroups per CU.  Each
+ * class is one persistent launch whose points are cut into one equal,
+ * contiguous chunk per workgroup; each workgroup walks the table runs of its
+ * chunk and re-stages its LDS copy of the table only when the table changes.
  * Uploads the plan and synchronises `stream`.
  */
 pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
@@ -223,7 +225,11 @@ pwl_status pwl_batch_capture(pwl_batch* bt, const float* x, const float* g, floa
                              void* stream);
 pwl_status pwl_batch_replay(pwl_batch* bt, void* stream);
 
-/* pwl_batch_info - shape of a batch (outputs nullable): tables, points, dv length, grids, runs. */
+/*
+ * pwl_batch_info - shape of a batch (outputs nullable): tables, points, dv
+ * length, and per direction the workgroups and table runs summed over the
+ * launches of one call.
+ */
 pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int64_t* dv_len, int32_t* grid_fwd,
                           int32_t* grid_bwd, int32_t* runs_fwd, int32_t* runs_bwd);
 

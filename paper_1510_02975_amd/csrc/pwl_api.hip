@@ -220,7 +220,6 @@ size_t layout(pwl::TableDev* td, char* base, int N, int K, int G) {
   td->values64 = reinterpret_cast<double*>(take(sizeof(double) * (N + 1)));
   td->status = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * 4));
   td->totals = reinterpret_cast<double*>(take(sizeof(double) * G));
-  td->ucell = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * (N + 1)));
   return off;
 }
 
@@ -420,25 +419,79 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
 
 namespace {
 
-// Cuts points [0, P) into `grid` chunks of equal size (boundaries on multiples
-// of 4 points so chunks keep the 16-byte phase of the arrays) and lists the
-// table runs of every chunk.
-void plan_runs(const int64_t* offsets, int T, int64_t P, int grid, std::vector<pwl::BatchRun>* runs,
+// Runs of one launch over the tables listed in `cls` (increasing table
+// order).  The class's points, taken in that order, are cut into `grid`
+// chunks of equal size; a chunk boundary inside a table is rounded down to a
+// multiple of 4 points of the global arrays (not below the table's first
+// point), so chunks keep the arrays' 16-byte phase.
+void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, std::vector<pwl::BatchRun>* runs,
                std::vector<int32_t>* run_begin) {
   runs->clear();
   run_begin->assign(grid + 1, 0);
-  int t = 0;
+  const int C = (int)cls.size();
+  std::vector<int64_t> voff(C + 1, 0);
+  for (int j = 0; j < C; ++j) voff[j + 1] = voff[j] + (offsets[cls[j] + 1] - offsets[cls[j]]);
+  const int64_t P = voff[C];
+  if (P == 0) return;
+  // boundary w: class table bj[w] at absolute point bp[w]; bj[grid] = C is the end
+  std::vector<int> bj(grid + 1, C);
+  std::vector<int64_t> bp(grid + 1, 0);
+  int j = 0;
+  for (int w = 0; w < grid; ++w) {
+    const int64_t v = (int64_t)((__int128)P * w / grid);   // < P
+    while (voff[j + 1] <= v) ++j;
+    const int64_t first = offsets[cls[j]];
+    bj[w] = j;
+    bp[w] = std::max(first, (first + (v - voff[j])) & ~(int64_t)3);
+  }
   for (int w = 0; w < grid; ++w) {
     (*run_begin)[w] = (int32_t)runs->size();
-    const int64_t c0 = (w == 0) ? 0 : ((int64_t)((__int128)P * w / grid) & ~(int64_t)3);
-    const int64_t c1 = (w == grid - 1) ? P : ((int64_t)((__int128)P * (w + 1) / grid) & ~(int64_t)3);
-    while (t < T && offsets[t + 1] <= c0) ++t;
-    for (int u = t; u < T && offsets[u] < c1; ++u) {
-      const int64_t b = std::max(c0, offsets[u]), e = std::min(c1, offsets[u + 1]);
-      if (b < e) runs->push_back(pwl::BatchRun{u, 0, b, e});
+    for (int jj = bj[w]; jj < C && jj <= bj[w + 1]; ++jj) {
+      const int u = cls[jj];
+      const int64_t b0 = (jj == bj[w]) ? bp[w] : offsets[u];
+      const int64_t e0 = (jj == bj[w + 1]) ? bp[w + 1] : offsets[u + 1];
+      if (b0 < e0) runs->push_back(pwl::BatchRun{u, 0, b0, e0});
     }
   }
   (*run_begin)[grid] = (int32_t)runs->size();
+}
+
+struct ClassPlan {
+  std::vector<pwl::BatchRun> runs;
+  std::vector<int32_t> begin;
+  int grid = 0;
+  size_t lds = 0;
+};
+
+// Splits the tables by LDS footprint: those that fit `want` workgroups per CU
+// and the larger ones, each class with its own grid.  A class without points
+// gets no launch unless no class has points (then one empty launch remains,
+// so a call always launches something).
+std::vector<ClassPlan> plan_classes(const pwl_table* const* tables, int T, const int64_t* offsets, bool backward,
+                                    int num_cu, int max_lds, int want) {
+  const size_t lim = (size_t)max_lds / (size_t)std::max(1, want);
+  std::vector<int> cls[2];
+  size_t lds[2] = {0, 0};
+  int64_t pts[2] = {0, 0};
+  for (int i = 0; i < T; ++i) {
+    const size_t l = pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward);
+    const int c = (l <= lim) ? 0 : 1;
+    cls[c].push_back(i);
+    lds[c] = std::max(lds[c], l);
+    pts[c] += offsets[i + 1] - offsets[i];
+  }
+  std::vector<ClassPlan> out;
+  for (int c = 0; c < 2; ++c) {
+    if (cls[c].empty()) continue;
+    if (pts[c] == 0 && (pts[0] + pts[1] > 0 || !out.empty())) continue;
+    ClassPlan p;
+    p.lds = lds[c];
+    const int by_lds = (int)std::max<size_t>(1, (size_t)max_lds / std::max<size_t>(p.lds, 1));
+    p.grid = num_cu * std::max(1, std::min(want, by_lds));
+    plan_runs(offsets, cls[c], p.grid, &p.runs, &p.begin);
+    out.push_back(std::move(p));
+  }
+  return out;
 }
 
 }  // namespace
@@ -457,7 +510,6 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   int dev = 0, num_cu = 1, max_lds = 0;
   pwl_status st = device_ready(&dev, &num_cu, &max_lds);
   if (st != PWL_OK) return st;
-  size_t lds_f = 0, lds_b = 0;
   std::vector<pwl::BatchTable> hb(T);
   int64_t dv_len = 0;
   for (int i = 0; i < T; ++i) {
@@ -466,56 +518,56 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
     hb[i].t = eval_view(tables[i]);
     hb[i].dv_off = dv_len;
     dv_len += tables[i]->bp.N + 1;
-    lds_f = std::max(lds_f, pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, false));
-    lds_b = std::max(lds_b, pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, true));
   }
   const pwl::LaunchConfig c = pwl::get_launch(PWL_KERNEL_BATCH);
-  auto grid_for = [&](size_t lds) {
-    const int by_lds = (int)std::max<size_t>(1, (size_t)max_lds / std::max<size_t>(lds, 1));
-    return num_cu * std::max(1, std::min(c.wg_per_cu, by_lds));
-  };
-  const int gf = grid_for(lds_f), gb = grid_for(lds_b);
-  const int64_t P = offsets[T];
-  std::vector<pwl::BatchRun> rf, rb;
-  std::vector<int32_t> bf, bb;
-  plan_runs(offsets, T, P, gf, &rf, &bf);
-  plan_runs(offsets, T, P, gb, &rb, &bb);
-  // one allocation: tables, forward runs and starts, backward runs and starts
+  const std::vector<ClassPlan> pf = plan_classes(tables, T, offsets, false, num_cu, max_lds, c.wg_per_cu);
+  const std::vector<ClassPlan> pb = plan_classes(tables, T, offsets, true, num_cu, max_lds, c.wg_per_cu);
+  // one allocation: tables, then runs and starts of every forward and backward launch
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
-  const size_t o_rf = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, rf.size()));
-  const size_t o_bf = take(sizeof(int32_t) * bf.size());
-  const size_t o_rb = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, rb.size()));
-  const size_t o_bb = take(sizeof(int32_t) * bb.size());
+  std::vector<size_t> o_runs, o_beg;
+  for (const auto* v : {&pf, &pb})
+    for (const ClassPlan& p : *v) {
+      o_runs.push_back(take(sizeof(pwl::BatchRun) * std::max<size_t>(1, p.runs.size())));
+      o_beg.push_back(take(sizeof(int32_t) * p.begin.size()));
+    }
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, off);
   if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
   char* b = static_cast<char*>(base);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  pwl_batch* bt = new pwl_batch{};
+  bt->bl.nfwd = (int32_t)pf.size();
+  bt->bl.nbwd = (int32_t)pb.size();
   e = hipMemcpyAsync(b + o_tab, hb.data(), sizeof(pwl::BatchTable) * T, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && !rf.empty())
-    e = hipMemcpyAsync(b + o_rf, rf.data(), sizeof(pwl::BatchRun) * rf.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(b + o_bf, bf.data(), sizeof(int32_t) * bf.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && !rb.empty())
-    e = hipMemcpyAsync(b + o_rb, rb.data(), sizeof(pwl::BatchRun) * rb.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(b + o_bb, bb.data(), sizeof(int32_t) * bb.size(), hipMemcpyHostToDevice, s);
+  size_t k = 0;
+  for (int dir = 0; dir < 2; ++dir) {
+    const std::vector<ClassPlan>& v = dir ? pb : pf;
+    for (size_t i = 0; i < v.size(); ++i, ++k) {
+      const ClassPlan& p = v[i];
+      if (e == hipSuccess && !p.runs.empty())
+        e = hipMemcpyAsync(b + o_runs[k], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
+                           hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b + o_beg[k], p.begin.data(), sizeof(int32_t) * p.begin.size(), hipMemcpyHostToDevice, s);
+      pwl::BatchPlan& d = dir ? bt->bl.bwd[i] : bt->bl.fwd[i];
+      d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[k]), reinterpret_cast<int32_t*>(b + o_beg[k]),
+                         p.grid, (int32_t)p.runs.size(), p.lds};
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     (void)hipFree(base);
+    delete bt;
     return fail(PWL_EHIP, "batch upload failed: %s", hipGetErrorString(e));
   }
-  pwl_batch* bt = new pwl_batch{};
   bt->device = dev;
   bt->T = T;
-  bt->npoints = P;
+  bt->npoints = offsets[T];
   bt->base = base;
   bt->bl.tables = reinterpret_cast<pwl::BatchTable*>(b + o_tab);
   bt->bl.dv_len = dv_len;
-  bt->bl.fwd = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_rf), reinterpret_cast<int32_t*>(b + o_bf),
-                              gf, (int32_t)rf.size(), lds_f};
-  bt->bl.bwd = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_rb), reinterpret_cast<int32_t*>(b + o_bb),
-                              gb, (int32_t)rb.size(), lds_b};
   *out = bt;
   return PWL_OK;
 }
@@ -613,10 +665,19 @@ pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int
   if (T) *T = bt->T;
   if (npoints) *npoints = bt->npoints;
   if (dv_len) *dv_len = bt->bl.dv_len;
-  if (grid_fwd) *grid_fwd = bt->bl.fwd.grid;
-  if (grid_bwd) *grid_bwd = bt->bl.bwd.grid;
-  if (runs_fwd) *runs_fwd = bt->bl.fwd.nruns;
-  if (runs_bwd) *runs_bwd = bt->bl.bwd.nruns;
+  int32_t gf = 0, gb = 0, rf = 0, rb = 0;
+  for (int k = 0; k < bt->bl.nfwd; ++k) {
+    gf += bt->bl.fwd[k].grid;
+    rf += bt->bl.fwd[k].nruns;
+  }
+  for (int k = 0; k < bt->bl.nbwd; ++k) {
+    gb += bt->bl.bwd[k].grid;
+    rb += bt->bl.bwd[k].nruns;
+  }
+  if (grid_fwd) *grid_fwd = gf;
+  if (grid_bwd) *grid_bwd = gb;
+  if (runs_fwd) *runs_fwd = rf;
+  if (runs_bwd) *runs_bwd = rb;
   return PWL_OK;
 }
 

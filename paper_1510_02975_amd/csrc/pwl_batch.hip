@@ -1,10 +1,12 @@
 // Batched evaluation of many tables of uneven size over uneven point counts
-// in one persistent launch.
+// in one persistent launch per table class.
 //
 // The points of all tables are concatenated (table t owns [off_t, off_{t+1})).
-// The host cuts the concatenation into one contiguous, equally sized chunk
-// per workgroup and lists, per workgroup, the (table, begin, end) runs its
-// chunk covers.  A workgroup walks its runs in order, re-staging the LDS
+// Tables are split into at most two classes by LDS footprint (those that fit
+// the configured workgroups per CU, and the larger ones).  Per class, the
+// host cuts the class's points into one contiguous, equally sized chunk per
+// workgroup and lists, per workgroup, the (table, begin, end) runs its chunk
+// covers.  A workgroup walks its runs in order, re-staging the LDS
 // table only when the table changes, and streams each run with the same
 // vectorised body as the single-table evaluator.  The fused backward keeps a
 // workgroup's dL/dv of the current table in FP64 LDS and flushes it with
@@ -128,18 +130,10 @@ inline bool same_phase(const void* a, const void* b) {
   return b == nullptr || ((reinterpret_cast<uintptr_t>(a) ^ reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
 }
 
-}  // namespace
-
-hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
-                        float* dv, hipStream_t s) {
-  const LaunchConfig c = get_launch(PWL_KERNEL_BATCH);
-  const bool backward = g != nullptr;
-  const BatchPlan& p = backward ? bl.bwd : bl.fwd;
-  const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
-                   (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
-  const int v = vec ? 1 : 0;
+hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchConfig& c, const float* x,
+                       const float* g, float* y, float* dx, float* dv, int v, hipStream_t s) {
   const dim3 grid(p.grid), block(c.block);
-  if (!backward) {
+  if (g == nullptr) {
     switch (c.unroll) {
       case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
       case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
@@ -147,8 +141,6 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
     }
     return hipGetLastError();
   }
-  const int64_t zgrid = std::min<int64_t>(1024, (bl.dv_len + 255) / 256);
-  hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::max<int64_t>(1, zgrid)), dim3(256), 0, s, dv, bl.dv_len);
   const int key = (y != nullptr ? 2 : 0) | (dx != nullptr ? 1 : 0);
 #define PWL_BB(UU, A, B)                                                                              \
   hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, g, \
@@ -167,6 +159,27 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
   }
 #undef PWL_BB_U
 #undef PWL_BB
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
+                        float* dv, hipStream_t s) {
+  const LaunchConfig c = get_launch(PWL_KERNEL_BATCH);
+  const bool backward = g != nullptr;
+  const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
+                   (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
+  const int v = vec ? 1 : 0;
+  if (backward) {
+    const int64_t zgrid = std::min<int64_t>(1024, (bl.dv_len + 255) / 256);
+    hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::max<int64_t>(1, zgrid)), dim3(256), 0, s, dv, bl.dv_len);
+  }
+  const int np = backward ? bl.nbwd : bl.nfwd;
+  for (int k = 0; k < np; ++k) {
+    const hipError_t e = launch_plan(bl, backward ? bl.bwd[k] : bl.fwd[k], c, x, g, y, dx, dv, v, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

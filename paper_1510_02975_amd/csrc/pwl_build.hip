@@ -3,7 +3,7 @@
 //   optimal partition (Sec. III-B1):
 //     k_density_totals   FP64 |f''|^(2/5) on the fine grid, trapezoid sum per workgroup
 //     k_invert_knots     FP64 prefix of those sums, targets i S_M / N, linear inversion;
-//                        per knot also its map cell and, for the interpolant, f(x_i)
+//                        per knot also, for the interpolant, f(x_i)
 //   every table:
 //     k_finalize         one workgroup: uniform knots (Sec. IV) when asked, the
 //                        uniform index map, the knot-collapse check, for the
@@ -99,13 +99,12 @@ __device__ double uniform_knot(const BuildParams& bp, int k) {
   return x;
 }
 
-// Everything a knot needs once its position is known: FP64 and FP32 copies,
-// its map cell (interior knots) and, for the interpolant, f at the FP32 knot.
+// Everything a knot needs once its position is known: FP64 and FP32 copies
+// and, for the interpolant, f at the FP32 knot.
 __device__ void emit_knot(const BuildParams& bp, const TableDev& td, int k, double x) {
   const float x32 = (float)x;
   td.knots64[k] = x;
   td.knots[k] = x32;
-  if (k >= 1 && k <= bp.N - 1) td.ucell[k] = map_cell(x32, bp.a32, bp.scale32, bp.K);
   if (bp.values == PWL_INTERP) td.values[k] = f_value32(bp.f, x32);
 }
 
@@ -193,9 +192,10 @@ __global__ __launch_bounds__(kScanThreads) void k_invert_knots(BuildParams bp, T
 constexpr int kFinalizeThreads = 1024;
 constexpr int kRowsPerThread = (PWL_MAX_N + 1 + kFinalizeThreads - 1) / kFinalizeThreads;
 
-// Everything after the knots, in one workgroup:
-//  1. (uniform partition) the knots x_k = a + (b - a) k / N, their cells and
-//     interpolant values;
+// Everything after the knots, in one workgroup that keeps the knots and their
+// map cells in LDS (every later step reads them several times):
+//  1. (uniform partition) the knots x_k = a + (b - a) k / N and their
+//     interpolant values; otherwise the knots the inversion wrote;
 //  2. per segment k: its cells of the uniform index map lo[u] = #{interior
 //     knots with cell < u} - segment k owns (cell(x_k), cell(x_{k+1})], with
 //     cell(x_0) = -1 and cell(x_N) = K - 1, so each cell is written once when
@@ -214,25 +214,42 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   double* R = A + n;      // reciprocal diagonal during the solve
   double* Cu = R + n;
   double* D = Cu + n;
+  float* X = reinterpret_cast<float*>(D + n);        // [N+1] FP32 knots
+  uint16_t* U = reinterpret_cast<uint16_t*>(X + n);  // [N+1] map cell of each interior knot
   __shared__ int s_collapsed, s_maxc;
   if (tid == 0) {
     s_collapsed = 0;
     s_maxc = 0;
   }
-  if (bp.partition == PWL_UNIFORM)
-    for (int k = tid; k <= N; k += kFinalizeThreads) emit_knot(bp, td, k, uniform_knot(bp, k));
+  // 1. knots (and, for the uniform interpolant, the values) into LDS
+  const bool uniform = bp.partition == PWL_UNIFORM;
+  for (int k = tid; k <= N; k += kFinalizeThreads) {
+    float x32;
+    if (uniform) {
+      const double x = uniform_knot(bp, k);
+      x32 = (float)x;
+      td.knots64[k] = x;
+      td.knots[k] = x32;
+      if (bp.values == PWL_INTERP) D[k] = (double)f_value32(bp.f, x32);
+    } else {
+      x32 = td.knots[k];
+      if (bp.values == PWL_INTERP) D[k] = (double)td.values[k];
+    }
+    X[k] = x32;
+    U[k] = (k >= 1 && k <= N - 1) ? (uint16_t)map_cell(x32, bp.a32, bp.scale32, bp.K) : (uint16_t)0;
+  }
   __syncthreads();
 
   // 2. map, collapse check, deepest cell
   int run = 0, bad = 0;
   for (int k = tid; k < N; k += kFinalizeThreads) {
-    const int u0 = (k == 0) ? -1 : td.ucell[k];
-    const int u1 = (k + 1 == N) ? bp.K - 1 : td.ucell[k + 1];
+    const int u0 = (k == 0) ? -1 : (int)U[k];
+    const int u1 = (k + 1 == N) ? bp.K - 1 : (int)U[k + 1];
     for (int u = u0 + 1; u <= u1; ++u) td.lo[u] = (uint16_t)k;
-    if (!(td.knots[k + 1] > td.knots[k])) bad = 1;
-    if (k >= 1 && (k == 1 || td.ucell[k - 1] != u0)) {   // first interior knot of its cell
+    if (!(X[k + 1] > X[k])) bad = 1;
+    if (k >= 1 && (k == 1 || (int)U[k - 1] != u0)) {   // first interior knot of its cell
       int r = 1;
-      while (k + r <= N - 1 && td.ucell[k + r] == u0) ++r;
+      while (k + r <= N - 1 && (int)U[k + r] == u0) ++r;
       run = max(run, r);
     }
   }
@@ -248,8 +265,8 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
       const int k = gid / kGaussPoints, q = gid % kGaussPoints;
       float sl = 0.0f, sr = 0.0f, h = 0.0f;
       if (k < N) {
-        const float xk = td.knots[k];
-        h = td.knots[k + 1] - xk;
+        const float xk = X[k];
+        h = X[k + 1] - xk;
         const float t = bp.gl.t[q];
         const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
         sl = (1.0f - t) * fq;
@@ -275,9 +292,9 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     for (int r = 0; r < kRowsPerThread; ++r) {
       const int i = tid + r * kFinalizeThreads;
       if (i >= n) break;
-      const double xi = (double)td.knots[i];
-      const double hl = (i > 0) ? xi - (double)td.knots[i - 1] : 0.0;
-      const double hr = (i < N) ? (double)td.knots[i + 1] - xi : 0.0;
+      const double xi = (double)X[i];
+      const double hl = (i > 0) ? xi - (double)X[i - 1] : 0.0;
+      const double hr = (i < N) ? (double)X[i + 1] - xi : 0.0;
       const double bl = (i > 0) ? A[i] : 0.0;
       const double br = (i < N) ? D[i] : 0.0;
       D[i] = bl + br;
@@ -328,8 +345,6 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
       if (i >= n) break;
       D[i] = D[i] / diag[r];
     }
-  } else {
-    for (int i = tid; i < n; i += kFinalizeThreads) D[i] = (double)td.values[i];
   }
   __syncthreads();
 
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     td.values[i] = (float)c;
   }
   for (int k = tid; k < N; k += kFinalizeThreads) {
-    const float x0 = td.knots[k], x1 = td.knots[k + 1];
+    const float x0 = X[k], x1 = X[k + 1];
     const double v0 = (double)(float)D[k], v1 = (double)(float)D[k + 1];
     const double h = (double)x1 - (double)x0;
     float4 r;

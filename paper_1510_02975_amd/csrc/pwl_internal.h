@@ -37,7 +37,6 @@ struct TableDev {
   uint32_t* status;   // [0] build flags (PWL_FLAG_*), [1] most knots in one map cell
   // build scratch
   double* totals;     // [G] per-workgroup density sums
-  int32_t* ucell;     // [N+1] map cell of every knot
 };
 
 // Everything an evaluation kernel needs about a table.
@@ -74,8 +73,10 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
   return b;
 }
 
-// PCR rows: 4 FP64 arrays.
-inline size_t finalize_lds_bytes(int N) { return 4 * sizeof(double) * (size_t)(N + 1); }
+// Table finalize: 4 FP64 PCR rows, the FP32 knots and their u16 map cells.
+inline size_t finalize_lds_bytes(int N) {
+  return (4 * sizeof(double) + sizeof(float) + sizeof(uint16_t)) * (size_t)(N + 1);
+}
 
 // Number of map cells for a table of N segments: two per segment on a uniform
 // partition (each cell then holds at most one knot), four on the optimal one.
@@ -117,9 +118,15 @@ struct BatchPlan {           // the runs of every workgroup of one launch
   size_t lds;
 };
 
+// Tables whose LDS footprint allows the configured workgroups per CU form one
+// class; the larger tables form a second class with fewer, bigger
+// workgroups.  Each class is one persistent launch.
+constexpr int kMaxBatchClasses = 2;
+
 struct BatchLaunch {
   BatchTable* tables;        // device [T]
-  BatchPlan fwd, bwd;
+  BatchPlan fwd[kMaxBatchClasses], bwd[kMaxBatchClasses];
+  int32_t nfwd, nbwd;        // launches per call
   int64_t dv_len;            // sum over tables of N + 1
 };
 

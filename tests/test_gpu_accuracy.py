@@ -1,0 +1,82 @@
+"""Approximation accuracy of GPU-built tables against the paper's error
+predictions, for the Lorentzian on [-20, 20] and Bessel J0 on [0, 50] on the
+optimal partition, N in {256, 1024, 4096}, interpolant and projection values.
+
+For each table the GPU builds:
+  * its L2 error (oracle quadrature on the downloaded table) is within the
+    schedule of Results 4-5: 5% of the prediction at N = 256, 1% at
+    N >= 1024, and the projection/interpolant ratio is 1/sqrt(6) within 2%
+    at N >= 1024 (Result 5);
+  * the empirical max |y_gpu - f(x)| over 2^27 uniform points (f in FP64 on
+    the host) matches the L-infinity prediction (h^2 |f''| / 8 for the
+    interpolant, h^2 |f''| / 12 for the projection) within the same
+    schedule, plus the FP32 evaluation slack: storing v and the slope in FP32
+    and one FMA add at most about 4 * 2^-24 max|f|, so 3e-7 max|f| is allowed.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests.gpu_util import device, fmax_abs, library, say
+
+pytestmark = pytest.mark.gpu
+
+EVAL_SLACK = 3e-7
+_cache = {}
+
+
+def _points(which):
+    """Seeded uniform points and f(x) in FP64, once per function."""
+    if which not in _cache:
+        _cache.clear()
+        spec = W.LORENTZ if which == "lorentz" else W.BESSEL
+        x = W.uniform_points(spec["a"], spec["b"], spec["n"], 0)
+        f = np.empty(len(x), np.float64)
+        step = 1 << 23
+        for i in range(0, len(x), step):
+            f[i:i + step] = O.f_value(spec["func"], spec["params"], x[i:i + step].astype(np.float64))
+        _cache[which] = (x, f)
+    return _cache[which]
+
+
+def _tol(N):
+    return 0.05 if N < 1024 else 0.01
+
+
+@pytest.mark.parametrize("which", ["lorentz", "j0"])
+@pytest.mark.parametrize("N", [256, 1024, 4096])
+def test_error_schedule_gpu_tables(which, N):
+    P = library()
+    dev = device()
+    spec = W.LORENTZ if which == "lorentz" else W.BESSEL
+    func, p, a, b = spec["func"], spec["params"], spec["a"], spec["b"]
+    pe = O.predicted_errors(func, p, a, b, N)
+    fmax = fmax_abs(func, p, a, b)
+    x_h, f_h = _points(which)
+    x = torch.from_numpy(x_h).to(dev)
+    tol = _tol(N)
+    l2 = {}
+    for vals in (O.INTERP, O.PROJ):
+        t = P.pwl_build(func, p, a, b, N, O.OPTIMAL, vals)
+        d = P.pwl_table_download(t)
+        X = d["knots"].astype(np.float64)
+        l2[vals] = O.l2_error(func, p, X, d["values64"])
+        r2 = l2[vals] / pe["l2"][(O.OPTIMAL, vals)]
+        y = P.pwl_eval(t, x).cpu().numpy().astype(np.float64)
+        emp = float(np.max(np.abs(y - f_h)))
+        pinf = pe["linf"][(O.OPTIMAL, vals)]
+        say("  %s N=%d %s: L2 %.4e (x%.4f of predicted), max|y-f| over 2^27 %.4e (x%.4f of predicted)"
+            % (which, N, "proj" if vals else "interp", l2[vals], r2, emp, emp / pinf))
+        assert abs(r2 - 1.0) <= tol, r2
+        assert emp <= (1.0 + tol) * pinf + EVAL_SLACK * fmax
+        # 2^27 points sample every segment densely: the maximum is found
+        assert emp >= (1.0 - tol) * pinf - EVAL_SLACK * fmax
+        t.free()
+    if N >= 1024:
+        r = math.sqrt(6.0) * l2[O.PROJ] / l2[O.INTERP]
+        assert abs(r - 1.0) <= 0.02, r

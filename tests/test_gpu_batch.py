@@ -140,3 +140,56 @@ def test_batch_misaligned_and_degenerate_shapes():
     _, _, dv = P.pwl_batch_eval_backward(bt, base[:0], base[:0], want=())
     assert torch.all(dv == 0.0) and dv.numel() == 301 + 41
     bt.free()
+
+
+def test_batch_two_lds_classes():
+    """N = 4096 tables need more LDS than the default workgroups per CU allow,
+    so they get a launch of their own next to the small tables; both launches
+    match the per-table evaluator bit for bit (y, dx) and dL/dv matches the
+    oracle, with the two classes interleaved in table order."""
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    big = P.pwl_build(O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, O.PROJ)
+    small = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 64, O.UNIFORM, O.INTERP)
+    mid = P.pwl_build(O.BESSEL_J0, (1.0,), 0.0, 50.0, 1000, O.OPTIMAL, O.INTERP)
+    tabs = [big, small, mid, big, small, big, mid]
+    counts = [70001, 5, 33333, 0, 128000, 3, 257]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n = int(offs[-1])
+    x = W.uniform_points(-25.0, 55.0, n, 4)
+    g = W.upstream_grad(n, 6)
+    xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
+    bt = P.pwl_batch_create(tabs, offs)
+    one = P.pwl_batch_create([small], [0, 5])
+    say("two classes: grid %d (one small class alone: %d), runs %d" % (bt.grid_fwd, one.grid_fwd, bt.runs_fwd))
+    assert bt.grid_fwd > one.grid_fwd
+    one.free()
+    y = P.pwl_batch_eval(bt, xt)
+    yb, dxb, dvb = P.pwl_batch_eval_backward(bt, xt, gt)
+    dvb = dvb.cpu().numpy()
+    for i, (t, o0, o1) in enumerate(zip(tabs, offs[:-1], offs[1:])):
+        d0, d1 = bt.dv_offsets[i], bt.dv_offsets[i + 1]
+        if o1 == o0:
+            assert np.all(dvb[d0:d1] == 0.0)
+            continue
+        assert torch.equal(y[o0:o1], P.pwl_eval(t, xt[o0:o1])), i
+        y1, dx1, _ = P.pwl_eval_backward(t, xt[o0:o1], gt[o0:o1])
+        assert torch.equal(yb[o0:o1], y1) and torch.equal(dxb[o0:o1], dx1), i
+        d = P.pwl_table_download(t)
+        X = d["knots"].astype(np.float64)
+        xs, gs = x[o0:o1].astype(np.float64), g[o0:o1].astype(np.float64)
+        _, _, dvr = O.evaluate_backward(X, d["values"].astype(np.float64), xs, gs)
+        _, _, wk = O.evaluate_backward(X, np.zeros(len(X)), xs, np.abs(gs))
+        assert np.all(np.abs(dvb[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30), i
+    bt.free()
+    # with one workgroup per CU every table fits one class
+    P.pwl_set_launch(P.KERNEL_BATCH, 4, 1024, 1)
+    try:
+        b1 = P.pwl_batch_create(tabs, offs)
+        assert torch.equal(P.pwl_batch_eval(b1, xt), y)
+        b1.free()
+    finally:
+        P.pwl_set_launch(P.KERNEL_BATCH, 0, 0, 0)
+    for t in (big, small, mid):
+        t.free()
