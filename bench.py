@@ -3,10 +3,14 @@
 Workload (the headline one): f(x) = exp(-x^2/2) on [-5, 5], quasi-optimal
 partition with N = 1024 segments, L2-projection vertex values; 2^28 FP32
 points x = clip(1.5 Z, -5, 5), seed 0, resident in HBM.  One step is one pass
-of the whole path: the table is rebuilt in place on the GPU (density scan,
+of the whole path: a table is rebuilt in place on the GPU (density scan,
 knot inversion, index map, quadrature, FP64 tridiagonal solve, packing) and
-then all 2^28 points are evaluated.  Input/output buffers rotate over three
-sets so no step reads the previous step's cache residue.
+then all 2^28 points are evaluated with it.  Two tables alternate: the build
+of step i + 1 runs on a second stream while step i evaluates (it waits for
+the evaluation that last used its table), so every step does all the work
+and the builds overlap the evaluations.  The same steps run back to back on
+one stream are reported too ("serial_step_gpoints_s").  Input/output buffers
+rotate over three sets so no step reads the previous step's cache residue.
 
 Prints one JSON line.  Secondary figures ride along in "extra": the fused
 forward+backward on the gradient workload, direct expf, copy bandwidth, the
@@ -14,7 +18,7 @@ Lorentzian and J0 tables at N = 256, 1024, 4096, and the many-table workload
 (one batched launch, its graph replay, the fused backward, and one launch per
 table).
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 20]
 """
 
 import argparse
@@ -63,20 +67,62 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
-def event_pairs(torch, k):
-    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+class Marks:
+    """Timing-only HIP events on the current stream, created with
+    hipEventDisableSystemFence: recording one takes no system-scope fence, so
+    it neither writes back nor invalidates the caches between the kernels it
+    separates (a default event does both).  The HIP runtime is the one torch
+    loaded (same soname), so torch's stream handles are valid here."""
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, torch, count):
+        import ctypes
+        self.ctypes = ctypes
+        self.torch = torch
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = []
+        for _ in range(count):
+            e = ctypes.c_void_p()
+            self._check(self.hip.hipEventCreateWithFlags(ctypes.byref(e), self.DISABLE_SYSTEM_FENCE))
+            self.ev.append(e)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise RuntimeError("HIP event call failed with status %d" % rc)
+
+    def record(self, i, stream=None):
+        s = stream if stream is not None else self.torch.cuda.current_stream()
+        self._check(self.hip.hipEventRecord(self.ev[i], s.cuda_stream))
+
+    def ms(self, i, j):
+        out = self.ctypes.c_float()
+        self._check(self.hip.hipEventElapsedTime(self.ctypes.byref(out), self.ev[i], self.ev[j]))
+        return out.value
+
+    def free(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(e)
+        self.ev = []
 
 
-def timed_median(torch, fn, reps=20, warm=3):
+def timed_median(torch, fn, reps=20, warm=30):
+    """Median launch time after `warm` untimed launches (enough sustained load
+    for the GPU to reach its steady clocks)."""
     for _ in range(warm):
         fn(0)
-    ev = event_pairs(torch, reps)
-    for i, (s, e) in enumerate(ev):
-        s.record()
+    m = Marks(torch, 2 * reps)
+    for i in range(reps):
+        m.record(2 * i)
         fn(i)
-        e.record()
+        m.record(2 * i + 1)
     torch.cuda.synchronize()
-    return float(np.median([s.elapsed_time(e) for s, e in ev])) * 1e-3
+    t = float(np.median([m.ms(2 * i, 2 * i + 1) for i in range(reps)])) * 1e-3
+    m.free()
+    return t
 
 
 def cpu_baseline_leg(spec, x_sample, y_gpu_sample, seconds):
@@ -179,6 +225,21 @@ def ingest_trace(trace_dir, out_md, command):
     for (name, grid, wg), d in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
         lines.append("| %s | %d | %d | %d | %.2f | %.2f | %.2f | %.2f |" % (
             name, grid, wg, len(d), float(np.mean(d)), float(np.median(d)), min(d), max(d)))
+    # the headline steps: every dispatch before the first copy-kernel launch
+    seq = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]),
+                  int(r["Grid_Size_X"])) for r in trace)
+    first_copy = min([s0 for s0, _, nm, _ in seq if nm.endswith("k_copy")] or [float("inf")])
+    head = [(s0, e0, nm, g) for s0, e0, nm, g in seq if s0 < first_copy]
+    if head:
+        lines += ["", "## Headline steps (the dispatches before the first copy-kernel launch)", "",
+                  "| kernel | grid | calls | average us | median us | min us | max us |",
+                  "|---|---|---|---|---|---|---|"]
+        hg = {}
+        for s0, e0, nm, g in head:
+            hg.setdefault((nm, g), []).append((e0 - s0) / 1e3)
+        for (nm, g), d in sorted(hg.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("| %s | %d | %d | %.2f | %.2f | %.2f | %.2f |" % (
+                nm, g, len(d), float(np.mean(d)), float(np.median(d)), min(d), max(d)))
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -265,7 +326,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
@@ -296,55 +357,98 @@ def main():
     sets = 3
     xs = [torch.from_numpy(x_host).to(dev) for _ in range(sets)]
     ys = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(sets)]
-    table = P.pwl_build(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"],
-                        spec["partition"], spec["values"])
+    # two tables: step i builds table i % 2 on a side stream while step i - 1
+    # evaluates the other one on the main stream
+    tables = [P.pwl_build(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"],
+                          spec["partition"], spec["values"]) for _ in range(2)]
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()   # default priority
 
-    def rebuild():
-        P.pwl_rebuild(table, spec["func"], spec["params"], spec["a"], spec["b"], spec["partition"],
-                      spec["values"])
+    def rebuild(t, stream):
+        P.pwl_rebuild(t, spec["func"], spec["params"], spec["a"], spec["b"], spec["partition"],
+                      spec["values"], stream=stream)
+
+    def run_steps(steps, marks=None):
+        """Pipelined steps: the evaluation of step i waits for its table's
+        build; the build of step i + 1 waits for the evaluation (step i - 1)
+        that last used its table."""
+        built = [torch.cuda.Event(), torch.cuda.Event()]
+        used = [torch.cuda.Event(), torch.cuda.Event()]
+        rebuild(tables[0], side)
+        built[0].record(side)
+        for i in range(steps):
+            k = i % 2
+            main.wait_event(built[k])
+            if marks:
+                marks.record(2 * i, main)
+            P.pwl_eval(tables[k], xs[i % sets], ys[i % sets], stream=main)
+            if marks:
+                marks.record(2 * i + 1, main)
+            used[k].record(main)
+            if i + 1 < steps:
+                if i >= 1:
+                    side.wait_event(used[1 - k])
+                rebuild(tables[1 - k], side)
+                built[1 - k].record(side)
+
+    def serial_steps(steps, marks=None):
+        for i in range(steps):
+            if marks:
+                marks.record(2 * i, main)
+            rebuild(tables[0], main)
+            if marks:
+                marks.record(2 * i + 1, main)
+            P.pwl_eval(tables[0], xs[i % sets], ys[i % sets], stream=main)
+        if marks:
+            marks.record(2 * steps, main)
 
     log("warmup %d" % args.warmup)
-    for i in range(args.warmup):
-        rebuild()
-        P.pwl_eval(table, xs[i % sets], ys[i % sets])
-    assert P.pwl_table_check(table) == 0
+    run_steps(args.warmup)
+    for t in tables:
+        assert P.pwl_table_check(t) == 0
     torch.cuda.synchronize()
 
     log("timing %d steps" % args.steps)
-    # one event between the build and the evaluation of a step and one after
-    # the evaluation (which also starts the next step's build)
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps + 1)]
+    # events around every evaluation
+    marks = Marks(torch, 2 * args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    marks[0].record()
-    for i in range(args.steps):
-        rebuild()
-        marks[2 * i + 1].record()
-        P.pwl_eval(table, xs[i % sets], ys[i % sets])
-        marks[2 * i + 2].record()
+    run_steps(args.steps, marks)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    eval_s = float(np.mean([marks[2 * i + 1].elapsed_time(marks[2 * i + 2])
-                            for i in range(args.steps)])) * 1e-3
-    build_s = float(np.mean([marks[2 * i].elapsed_time(marks[2 * i + 1])
-                             for i in range(args.steps)])) * 1e-3
+    eval_s = float(np.mean([marks.ms(2 * i, 2 * i + 1) for i in range(args.steps)])) * 1e-3
+    marks.free()
+    m_cpu = min(n, 1 << args.cpu_sample_log2)
+    y_sample = ys[(args.steps - 1) % sets][:m_cpu].cpu().numpy()   # before anything reuses ys
+    # the same steps without the overlap, for reference
+    serial_steps(args.warmup)
+    smarks = Marks(torch, 2 * args.steps + 1)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    serial_steps(args.steps, smarks)
+    torch.cuda.synchronize()
+    serial_wall = time.perf_counter() - ts0
+    # build time of a step when nothing else runs (the serial reference)
+    build_s = float(np.mean([smarks.ms(2 * i, 2 * i + 1) for i in range(args.steps)])) * 1e-3
+    serial_eval_s = float(np.mean([smarks.ms(2 * i + 1, 2 * i + 2) for i in range(args.steps)])) * 1e-3
+    smarks.free()
     value = n * args.steps / wall / 1e9
     achieved = FWD_BYTES_PER_POINT * n / eval_s / 1e9
     log("step %.3f ms, eval kernel %.1f us (%.0f GB/s), build %.1f us"
         % (wall / args.steps * 1e3, eval_s * 1e6, achieved, build_s * 1e6))
     traffic = measured_traffic()
-    m_cpu = min(n, 1 << args.cpu_sample_log2)
-    y_sample = ys[(args.steps - 1) % sets][:m_cpu].cpu().numpy()   # before the extras reuse ys
 
     extra = {"eval_kernel_us": eval_s * 1e6, "build_us": build_s * 1e6,
              "eval_only_gpoints_s": n / eval_s / 1e9,
+             "serial_step_gpoints_s": n * args.steps / serial_wall / 1e9,
+             "serial_eval_kernel_us": serial_eval_s * 1e6,
              "kernel_source_hash": kernel_source_hash()}
+    # the copy kernel: the practical HBM ceiling, and the byte-counter calibration
+    t_copy = timed_median(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % sets]))
+    extra["copy_GBs"] = 8.0 * n / t_copy / 1e9
     if not args.no_extra:
-        log("extras: copy, direct expf, fused forward+backward")
-        xa, ya = xs[0], ys[0]
-        t_copy = timed_median(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % sets]))
-        extra["copy_GBs"] = 8.0 * n / t_copy / 1e9
+        log("extras: direct expf, fused forward+backward")
         for fast in (0, 1):
             t = timed_median(torch, lambda i: P.pwl_direct_gaussian(xs[i % sets], ys[i % sets], 1.0, 1.0, fast))
             extra["direct_%s_gpoints_s" % ("fast_expf" if fast else "expf")] = n / t / 1e9
@@ -391,7 +495,8 @@ def main():
         "config": {"workload": "gauss_optimal_n1024_proj_2^%d" % args.log2n,
                    "f": "exp(-x^2/2)", "domain": [-5.0, 5.0], "N": 1024, "partition": "optimal",
                    "values": "L2 projection", "points": n, "x": "clip(1.5 Z, -5, 5), seed 0",
-                   "step": "GPU table rebuild + forward evaluation of all points"},
+                   "step": "GPU table rebuild + forward evaluation of all points; the next step's "
+                           "rebuild (second table, second stream) overlaps this step's evaluation"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_eval_fwd", "algorithmic_bytes_per_launch": FWD_BYTES_PER_POINT * n},
@@ -400,7 +505,8 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
-    table.free()
+    for t in tables:
+        t.free()
     return 0
 
 

@@ -166,10 +166,15 @@ pwl_status pwl_eval(const pwl_table* t, const float* v_override, const float* x,
  * gradient g: y = v(x) (nullable), dx = g * v'(x) (nullable; 0 where x was
  * clamped, the left slope at x = b), dv[k] = sum over points of g times the
  * hat weight phi_k(x) (nullable; device [N+1]; OVERWRITTEN: each workgroup
- * sums its points in FP64 and the workgroup sums are combined with FP32
- * atomics, so the last bits depend on their order).  At least one of y, dx,
- * dv must be non-NULL.  This is the exact derivative of Algorithm 1 (the
- * paper gives none): dy/dx is the segment slope, dy/dv_k the hat weight.
+ * sums its points in FP64 and writes the sums, rounded to FP32, as one row
+ * of a per-table workspace; a second kernel adds the rows in FP64 in a fixed
+ * order, so dv is deterministic for a given launch shape).  At least one of
+ * y, dx, dv must be non-NULL.  This is the exact derivative of Algorithm 1
+ * (the paper gives none): dy/dx is the segment slope, dy/dv_k the hat weight.
+ * Workspace: (workgroups x (N+1)) floats owned by the table, allocated by
+ * the first call with dv that needs more (that call synchronises the
+ * device; freed with the table).  Calls with dv on one table share it, so
+ * they must not overlap in time: issue them on one stream.
  */
 pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const float* x,
                              const float* g, float* y, float* dx, float* dv, int64_t n, void* stream);
@@ -186,18 +191,21 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
 /*
  * pwl_batch_create - prepare the launches that evaluate T tables, table t on
  * the points [offsets[t], offsets[t+1]) of concatenated point arrays.
- *   tables[T]    tables on the current device; the batch keeps their device
- *                addresses and shapes, so free (or rebuild) a table only
- *                after freeing the batches that use it.
+ *   tables[T]    tables on the current device.  The batch copies each
+ *                table's evaluation data (records, knots, index map) into
+ *                its own memory here, so the tables may be freed or rebuilt
+ *                afterwards without affecting it (a rebuilt table needs a
+ *                new batch to be seen).
  *   offsets[T+1] HOST array, offsets[0] = 0, non-decreasing (empty tables
  *                allowed); offsets[T] is the total number of points.
  * Tables are split into at most two classes by LDS footprint: those that
- * fit the PWL_KERNEL_BATCH launch shape's workgroups per CU (at creation
- * time), and the larger ones, which run with fewer workgroups per CU.  Each
- * class is one persistent launch whose points are cut into one equal,
- * contiguous chunk per workgroup; each workgroup walks the table runs of its
- * chunk and re-stages its LDS copy of the table only when the table changes.
- * Uploads the plan and synchronises `stream`.
+ * fit the workgroups per CU of the PWL_KERNEL_BATCH (forward) or
+ * PWL_KERNEL_BATCH_BACKWARD launch shape current at creation, and the larger
+ * ones, which run with fewer workgroups per CU.  Each class is one
+ * persistent launch whose points are cut into one equal, contiguous chunk
+ * per workgroup; each workgroup walks the table runs of its chunk and
+ * re-stages its LDS copy of the table only when the table changes.
+ * Packs the copies, uploads the plan and synchronises `stream`.
  */
 pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
                             pwl_batch** out);
@@ -253,7 +261,8 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream);
 
 #define PWL_KERNEL_FORWARD 0    /* pwl_eval, pwl_locate   */
 #define PWL_KERNEL_BACKWARD 1   /* pwl_eval_backward      */
-#define PWL_KERNEL_BATCH 2      /* the batched evaluator  */
+#define PWL_KERNEL_BATCH 2      /* the batched forward    */
+#define PWL_KERNEL_BATCH_BACKWARD 3   /* the batched fused backward */
 
 /*
  * pwl_set_launch - process-wide launch shape of one evaluation kernel family:

@@ -353,7 +353,7 @@ def pwl_batch_free(batch):
     batch.free()
 
 
-KERNEL_FORWARD, KERNEL_BACKWARD, KERNEL_BATCH = 0, 1, 2
+KERNEL_FORWARD, KERNEL_BACKWARD, KERNEL_BATCH, KERNEL_BATCH_BACKWARD = 0, 1, 2, 3
 
 
 def pwl_set_launch(kernel, unroll=0, block=0, wg_per_cu=0):

@@ -38,6 +38,10 @@ struct pwl_table {
   pwl::TableDev td;
   void* base;
   size_t bytes;
+  // dL/dv partial sums of the fused backward (one row per workgroup),
+  // allocated by the first backward call that needs more
+  mutable float* part = nullptr;
+  mutable size_t part_cap = 0;   // floats
 };
 
 namespace {
@@ -266,7 +270,7 @@ pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double
   st = device_ready(&dev, nullptr, &max_lds);
   if (st != PWL_OK) return st;
   const size_t need = std::max(pwl::finalize_lds_bytes(bp.N),
-                               pwl::eval_lds_bytes(bp.N, pwl::map_cells_for(bp.N, PWL_OPTIMAL), true));
+                               pwl::batch_lds_bytes(bp.N, pwl::map_cells_for(bp.N, PWL_OPTIMAL), true));
   if (need > (size_t)max_lds)
     return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", N, need, max_lds);
   pwl::TableDev td;
@@ -346,6 +350,7 @@ pwl_status pwl_table_download(const pwl_table* t, float* knots, float* values, d
 void pwl_table_free(pwl_table* t) {
   if (t == nullptr) return;
   (void)hipFree(t->base);
+  if (t->part != nullptr) (void)hipFree(t->part);
   delete t;
 }
 
@@ -373,7 +378,26 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
   if (n == 0 && dv == nullptr) return PWL_OK;
   pwl_status st = check_table(t, &num_cu);
   if (st != PWL_OK) return st;
-  PWL_HIP(pwl::launch_eval_backward(eval_view(t), v_override, x, g, y, dx, dv, n, num_cu,
+  const pwl::EvalTable e = eval_view(t);
+  if (dv != nullptr && n > 0) {
+    const size_t need = pwl::backward_workspace_floats(e, x, g, y, dx, n, num_cu);
+    if (need > t->part_cap) {
+      if (t->part != nullptr) {
+        PWL_HIP(hipDeviceSynchronize());   // a previous call may still read the old rows
+        (void)hipFree(t->part);
+        t->part = nullptr;
+        t->part_cap = 0;
+      }
+      void* p = nullptr;
+      hipError_t me = hipMalloc(&p, need * sizeof(float));
+      if (me != hipSuccess)
+        return fail(PWL_ENOMEM, "hipMalloc(%zu) for the dL/dv partial sums failed: %s", need * sizeof(float),
+                    hipGetErrorString(me));
+      t->part = static_cast<float*>(p);
+      t->part_cap = need;
+    }
+  }
+  PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, t->part, n, num_cu,
                                     static_cast<hipStream_t>(stream)));
   return PWL_OK;
 }
@@ -419,30 +443,41 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
 
 namespace {
 
+// A table switch costs a workgroup about as long as streaming this many
+// points: staging a table image waits ~3 us on its loads while one of ~500
+// workgroups streams ~1.4 Gpoints/s.
+constexpr int64_t kStagePoints = 4096;
+
 // Runs of one launch over the tables listed in `cls` (increasing table
-// order).  The class's points, taken in that order, are cut into `grid`
-// chunks of equal size; a chunk boundary inside a table is rounded down to a
-// multiple of 4 points of the global arrays (not below the table's first
-// point), so chunks keep the arrays' 16-byte phase.
+// order).  The class's work, taken in that order, is cut into `grid` chunks
+// of equal cost, where a table with points costs kStagePoints (its staging)
+// plus its points, so a workgroup that meets many small tables gets fewer
+// points.  A chunk boundary inside a table is rounded down to a multiple of
+// 4 points of the global arrays (not below the table's first point), so
+// chunks keep the arrays' 16-byte phase.
 void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, std::vector<pwl::BatchRun>* runs,
                std::vector<int32_t>* run_begin) {
   runs->clear();
   run_begin->assign(grid + 1, 0);
   const int C = (int)cls.size();
-  std::vector<int64_t> voff(C + 1, 0);
-  for (int j = 0; j < C; ++j) voff[j + 1] = voff[j] + (offsets[cls[j] + 1] - offsets[cls[j]]);
-  const int64_t P = voff[C];
-  if (P == 0) return;
+  std::vector<int64_t> voff(C + 1, 0);   // cumulative cost
+  for (int j = 0; j < C; ++j) {
+    const int64_t pts = offsets[cls[j] + 1] - offsets[cls[j]];
+    voff[j + 1] = voff[j] + (pts > 0 ? kStagePoints + pts : 0);
+  }
+  const int64_t total = voff[C];
+  if (total == 0) return;
   // boundary w: class table bj[w] at absolute point bp[w]; bj[grid] = C is the end
   std::vector<int> bj(grid + 1, C);
   std::vector<int64_t> bp(grid + 1, 0);
   int j = 0;
   for (int w = 0; w < grid; ++w) {
-    const int64_t v = (int64_t)((__int128)P * w / grid);   // < P
-    while (voff[j + 1] <= v) ++j;
+    const int64_t v = (int64_t)((__int128)total * w / grid);   // < total
+    while (voff[j + 1] <= v) ++j;                                // skips tables without points
     const int64_t first = offsets[cls[j]];
+    const int64_t q = v - voff[j] - kStagePoints;                 // points of table j before the boundary
     bj[w] = j;
-    bp[w] = std::max(first, (first + (v - voff[j])) & ~(int64_t)3);
+    bp[w] = (q <= 0) ? first : std::max(first, (first + q) & ~(int64_t)3);
   }
   for (int w = 0; w < grid; ++w) {
     (*run_begin)[w] = (int32_t)runs->size();
@@ -450,7 +485,13 @@ void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, st
       const int u = cls[jj];
       const int64_t b0 = (jj == bj[w]) ? bp[w] : offsets[u];
       const int64_t e0 = (jj == bj[w + 1]) ? bp[w + 1] : offsets[u + 1];
-      if (b0 < e0) runs->push_back(pwl::BatchRun{u, 0, b0, e0});
+      if (b0 < e0) {
+        pwl::BatchRun r{};
+        r.table = u;
+        r.begin = b0;
+        r.end = e0;
+        runs->push_back(r);
+      }
     }
   }
   (*run_begin)[grid] = (int32_t)runs->size();
@@ -474,7 +515,7 @@ std::vector<ClassPlan> plan_classes(const pwl_table* const* tables, int T, const
   size_t lds[2] = {0, 0};
   int64_t pts[2] = {0, 0};
   for (int i = 0; i < T; ++i) {
-    const size_t l = pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward);
+    const size_t l = pwl::batch_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward);
     const int c = (l <= lim) ? 0 : 1;
     cls[c].push_back(i);
     lds[c] = std::max(lds[c], l);
@@ -510,25 +551,28 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   int dev = 0, num_cu = 1, max_lds = 0;
   pwl_status st = device_ready(&dev, &num_cu, &max_lds);
   if (st != PWL_OK) return st;
-  std::vector<pwl::BatchTable> hb(T);
-  int64_t dv_len = 0;
-  for (int i = 0; i < T; ++i) {
+  for (int i = 0; i < T; ++i)
     if (tables[i]->device != dev)
       return fail(PWL_EINVAL, "tables[%d] lives on device %d, current is %d", i, tables[i]->device, dev);
-    hb[i].t = eval_view(tables[i]);
-    hb[i].dv_off = dv_len;
-    dv_len += tables[i]->bp.N + 1;
-  }
-  const pwl::LaunchConfig c = pwl::get_launch(PWL_KERNEL_BATCH);
-  const std::vector<ClassPlan> pf = plan_classes(tables, T, offsets, false, num_cu, max_lds, c.wg_per_cu);
-  const std::vector<ClassPlan> pb = plan_classes(tables, T, offsets, true, num_cu, max_lds, c.wg_per_cu);
-  // one allocation: tables, then runs and starts of every forward and backward launch
+  const int want_f = pwl::get_launch(PWL_KERNEL_BATCH).wg_per_cu;
+  const int want_b = pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD).wg_per_cu;
+  std::vector<ClassPlan> plans[2] = {plan_classes(tables, T, offsets, false, num_cu, max_lds, want_f),
+                                     plan_classes(tables, T, offsets, true, num_cu, max_lds, want_b)};
+  // one allocation: tables, their deepest map cells, their images, then the
+  // runs and starts of every forward and backward launch
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
+  const size_t o_maxc = take(sizeof(int32_t) * T);
+  std::vector<size_t> o_img(T);
+  std::vector<int32_t> nvec(T);
+  for (int i = 0; i < T; ++i) {
+    nvec[i] = (int32_t)((pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, false) + 15) / 16);
+    o_img[i] = take(16 * (size_t)nvec[i]);
+  }
   std::vector<size_t> o_runs, o_beg;
-  for (const auto* v : {&pf, &pb})
-    for (const ClassPlan& p : *v) {
+  for (int dir = 0; dir < 2; ++dir)
+    for (const ClassPlan& p : plans[dir]) {
       o_runs.push_back(take(sizeof(pwl::BatchRun) * std::max<size_t>(1, p.runs.size())));
       o_beg.push_back(take(sizeof(int32_t) * p.begin.size()));
     }
@@ -537,15 +581,44 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
   char* b = static_cast<char*>(base);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  pwl_batch* bt = new pwl_batch{};
-  bt->bl.nfwd = (int32_t)pf.size();
-  bt->bl.nbwd = (int32_t)pb.size();
+  std::vector<pwl::BatchTable> hb(T);
+  std::vector<int64_t> dv_off(T);
+  int64_t dv_len = 0;
+  for (int i = 0; i < T; ++i) {
+    hb[i].t = eval_view(tables[i]);
+    hb[i].img = reinterpret_cast<float4*>(b + o_img[i]);
+    hb[i].nvec = nvec[i];
+    hb[i].pad = 0;
+    dv_off[i] = dv_len;
+    dv_len += tables[i]->bp.N + 1;
+  }
+  // images and deepest cells on the device, the cells back to the host
+  std::vector<int32_t> maxc(T, 0);
+  int32_t* d_maxc = reinterpret_cast<int32_t*>(b + o_maxc);
   e = hipMemcpyAsync(b + o_tab, hb.data(), sizeof(pwl::BatchTable) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = pwl::launch_batch_pack(reinterpret_cast<pwl::BatchTable*>(b + o_tab), T, d_maxc, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(maxc.data(), d_maxc, sizeof(int32_t) * T, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  // complete the run descriptors and upload the plans
+  pwl_batch* bt = new pwl_batch{};
+  bt->bl.nfwd = (int32_t)plans[0].size();
+  bt->bl.nbwd = (int32_t)plans[1].size();
   size_t k = 0;
   for (int dir = 0; dir < 2; ++dir) {
-    const std::vector<ClassPlan>& v = dir ? pb : pf;
-    for (size_t i = 0; i < v.size(); ++i, ++k) {
-      const ClassPlan& p = v[i];
+    for (size_t i = 0; i < plans[dir].size(); ++i, ++k) {
+      ClassPlan& p = plans[dir][i];
+      for (pwl::BatchRun& r : p.runs) {
+        const pwl_table* t = tables[r.table];
+        r.img = hb[r.table].img;
+        r.nvec = nvec[r.table];
+        r.dv_off = dv_off[r.table];
+        r.N = t->bp.N;
+        r.K = t->bp.K;
+        r.a32 = t->bp.a32;
+        r.b32 = t->bp.b32;
+        r.scale32 = t->bp.scale32;
+        r.maxc = maxc[r.table];
+      }
       if (e == hipSuccess && !p.runs.empty())
         e = hipMemcpyAsync(b + o_runs[k], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
                            hipMemcpyHostToDevice, s);
@@ -566,7 +639,6 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   bt->T = T;
   bt->npoints = offsets[T];
   bt->base = base;
-  bt->bl.tables = reinterpret_cast<pwl::BatchTable*>(b + o_tab);
   bt->bl.dv_len = dv_len;
   *out = bt;
   return PWL_OK;
@@ -697,7 +769,7 @@ pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t
 }
 
 pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32_t* wg_per_cu) {
-  if (kernel < 0 || kernel > 2) return fail(PWL_EINVAL, "unknown kernel family %d", kernel);
+  if (kernel < 0 || kernel > 3) return fail(PWL_EINVAL, "unknown kernel family %d", kernel);
   const pwl::LaunchConfig c = pwl::get_launch(kernel);
   if (unroll) *unroll = c.unroll;
   if (block) *block = c.block;

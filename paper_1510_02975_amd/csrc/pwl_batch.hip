@@ -23,56 +23,84 @@ namespace {
 
 using namespace stream;
 
-template <int U>
-__device__ __forceinline__ void batch_fwd_run(const EvalTable& t, const Smem& s, const float* __restrict__ x,
-                                              float* __restrict__ y, int64_t b, int64_t e, bool vec) {
-  switch (t.meta[1]) {
-    case 0:
-    case 1: fwd_range<U, 1>(t, s, x, y, b, e, vec, 0, 1); break;
-    case 2: fwd_range<U, 2>(t, s, x, y, b, e, vec, 0, 1); break;
-    case 3: fwd_range<U, 3>(t, s, x, y, b, e, vec, 0, 1); break;
-    case 4: fwd_range<U, 4>(t, s, x, y, b, e, vec, 0, 1); break;
-    default: fwd_range<U, 0>(t, s, x, y, b, e, vec, 0, 1); break;
-  }
+// The shape of a run's table as the streaming building blocks expect it (the
+// array pointers are unused: the table is already in LDS).
+__device__ __forceinline__ EvalTable run_table(const BatchRun& r) {
+  EvalTable t;
+  t.rec = nullptr;
+  t.knots = nullptr;
+  t.lo = nullptr;
+  t.meta = nullptr;
+  t.N = r.N;
+  t.K = r.K;
+  t.a32 = r.a32;
+  t.b32 = r.b32;
+  t.scale32 = r.scale32;
+  return t;
+}
+
+// Linear copy of n 16-byte words (descriptors or a table image) into LDS.
+__device__ __forceinline__ void copy_words(const float4* __restrict__ src, int n, float4* dst) {
+  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
 template <int U>
-__global__ __launch_bounds__(1024) void k_batch_fwd(const BatchTable* __restrict__ tabs,
-                                                    const BatchRun* __restrict__ runs,
+__device__ __forceinline__ void batch_fwd_run(const BatchRun& r, const Smem& s, const float* __restrict__ x,
+                                              float* __restrict__ y, bool vec) {
+  const EvalTable t = run_table(r);
+  switch (r.maxc) {
+    case 0:
+    case 1: fwd_range<U, 1>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+    case 2: fwd_range<U, 2>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+    case 3: fwd_range<U, 3>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+    case 4: fwd_range<U, 4>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+    default: fwd_range<U, 0>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+  }
+}
+
+// A workgroup walks its runs in blocks of kRunSlots descriptors held in LDS;
+// it re-stages the table image only when the table changes.
+template <int U>
+__global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__ runs,
                                                     const int32_t* __restrict__ run_begin,
                                                     const float* __restrict__ x, float* __restrict__ y,
                                                     int vec) {
   extern __shared__ float4 lds_f4[];
+  BatchRun* slots = reinterpret_cast<BatchRun*>(lds_f4);
+  float4* image = lds_f4 + kRunSlots * (int)(sizeof(BatchRun) / 16);
   const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
   int cur = -1;
-  EvalTable t;
-  Smem s;
-  for (int r = r0; r < r1; ++r) {
-    const BatchRun run = runs[r];
-    if (run.table != cur) {
-      __syncthreads();   // every thread is done with the previous table
-      t = tabs[run.table].t;
-      s = carve(lds_f4, t.N, t.K, false);
-      stage_table(t, nullptr, s);
-      __syncthreads();
-      cur = run.table;
+  for (int rb = r0; rb < r1; rb += kRunSlots) {
+    const int nr = min(kRunSlots, r1 - rb);
+    __syncthreads();   // every thread is done with the previous descriptors and table
+    copy_words(reinterpret_cast<const float4*>(runs + rb), nr * (int)(sizeof(BatchRun) / 16), lds_f4);
+    __syncthreads();
+    for (int q = 0; q < nr; ++q) {
+      const BatchRun r = slots[q];
+      if (r.table != cur) {
+        if (cur >= 0) __syncthreads();
+        copy_words(r.img, r.nvec, image);
+        __syncthreads();
+        cur = r.table;
+      }
+      batch_fwd_run<U>(r, carve(image, r.N, r.K, false), x, y, vec != 0);
     }
-    batch_fwd_run<U>(t, s, x, y, run.begin, run.end, vec != 0);
   }
 }
 
 template <int U, bool WY, bool WDX>
-__device__ __forceinline__ void batch_bwd_run(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+__device__ __forceinline__ void batch_bwd_run(const BatchRun& r, const Smem& s, const float* __restrict__ x,
                                               const float* __restrict__ g, float* __restrict__ y,
-                                              float* __restrict__ dx, int64_t b, int64_t e, bool vec) {
+                                              float* __restrict__ dx, bool vec) {
   using B = Bwd<U, WY, WDX, true>;
-  switch (t.meta[1]) {
+  const EvalTable t = run_table(r);
+  switch (r.maxc) {
     case 0:
-    case 1: B::template range<1>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
-    case 2: B::template range<2>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
-    case 3: B::template range<3>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
-    case 4: B::template range<4>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
-    default: B::template range<0>(t, s, x, g, y, dx, b, e, vec, 0, 1); break;
+    case 1: B::template range<1>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
+    case 2: B::template range<2>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
+    case 3: B::template range<3>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
+    case 4: B::template range<4>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
+    default: B::template range<0>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
   }
 }
 
@@ -83,41 +111,70 @@ __device__ __forceinline__ void flush_dv(const Smem& s, int N, float* __restrict
   }
 }
 
+// As k_batch_fwd; the current table's dL/dv is kept in FP64 LDS and flushed
+// with global FP32 atomics into the concatenated gradient whenever the table
+// changes and at the end.
 template <int U, bool WY, bool WDX>
-__global__ __launch_bounds__(1024) void k_batch_bwd(const BatchTable* __restrict__ tabs,
-                                                    const BatchRun* __restrict__ runs,
+__global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__ runs,
                                                     const int32_t* __restrict__ run_begin,
                                                     const float* __restrict__ x, const float* __restrict__ g,
                                                     float* __restrict__ y, float* __restrict__ dx,
                                                     float* __restrict__ dv, int vec) {
   extern __shared__ float4 lds_f4[];
+  BatchRun* slots = reinterpret_cast<BatchRun*>(lds_f4);
+  float4* image = lds_f4 + kRunSlots * (int)(sizeof(BatchRun) / 16);
   const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
-  int cur = -1;
-  EvalTable t;
-  Smem s;
-  int64_t dv_off = 0;
-  for (int r = r0; r < r1; ++r) {
-    const BatchRun run = runs[r];
-    if (run.table != cur) {
-      __syncthreads();   // every thread is done with the previous table
-      if (cur >= 0) {
-        flush_dv(s, t.N, dv + dv_off);
+  int cur = -1, curN = 0;
+  int64_t cur_off = 0;
+  Smem s = carve(image, 0, 0, true);
+  for (int rb = r0; rb < r1; rb += kRunSlots) {
+    const int nr = min(kRunSlots, r1 - rb);
+    __syncthreads();   // every thread is done with the previous descriptors
+    copy_words(reinterpret_cast<const float4*>(runs + rb), nr * (int)(sizeof(BatchRun) / 16), lds_f4);
+    __syncthreads();
+    for (int q = 0; q < nr; ++q) {
+      const BatchRun r = slots[q];
+      if (r.table != cur) {
+        if (cur >= 0) {
+          __syncthreads();   // every thread is done with the previous table
+          flush_dv(s, curN, dv + cur_off);
+          __syncthreads();
+        }
+        copy_words(r.img, r.nvec, image);
+        s = carve(image, r.N, r.K, true);
+        for (int k = threadIdx.x; k <= r.N; k += blockDim.x) s.dv[k] = 0.0;
         __syncthreads();
+        cur = r.table;
+        curN = r.N;
+        cur_off = r.dv_off;
       }
-      t = tabs[run.table].t;
-      dv_off = tabs[run.table].dv_off;
-      s = carve(lds_f4, t.N, t.K, true);
-      stage_table(t, nullptr, s);
-      for (int k = threadIdx.x; k <= t.N; k += blockDim.x) s.dv[k] = 0.0;
-      __syncthreads();
-      cur = run.table;
+      batch_bwd_run<U, WY, WDX>(r, s, x, g, y, dx, vec != 0);
     }
-    batch_bwd_run<U, WY, WDX>(t, s, x, g, y, dx, run.begin, run.end, vec != 0);
   }
   if (cur >= 0) {
     __syncthreads();
-    flush_dv(s, t.N, dv + dv_off);
+    flush_dv(s, curN, dv + cur_off);
   }
+}
+
+// One workgroup per table: its LDS image (records, knots with NaN outside
+// 1..N-1 up to the sentinel pad, index map, zero padding to whole 16-byte
+// words) and its deepest map cell.
+__global__ __launch_bounds__(256) void k_batch_pack(const BatchTable* __restrict__ tabs, int32_t* __restrict__ maxc) {
+  const BatchTable bt = tabs[blockIdx.x];
+  const EvalTable& t = bt.t;
+  const Smem s = carve(bt.img, t.N, t.K, false);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = tid; k < t.N; k += nt) s.rec[k] = t.rec[k];
+  const float qnan = __builtin_nanf("");
+  for (int k = tid; k < t.N + kKnotPad; k += nt) s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
+  const int nlo = (t.K + 2) & ~1;
+  for (int u = tid; u < nlo; u += nt) s.lo[u] = (u <= t.K) ? t.lo[u] : (uint16_t)0;
+  // zero the tail of the last word
+  uint8_t* end = reinterpret_cast<uint8_t*>(s.lo + nlo);
+  uint8_t* stop = reinterpret_cast<uint8_t*>(bt.img + bt.nvec);
+  for (uint8_t* p = end + tid; p < stop; p += nt) *p = 0;
+  if (tid == 0) maxc[blockIdx.x] = (int32_t)t.meta[1];
 }
 
 __global__ void k_batch_zero(float* __restrict__ p, int64_t n) {
@@ -135,15 +192,15 @@ hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchCo
   const dim3 grid(p.grid), block(c.block);
   if (g == nullptr) {
     switch (c.unroll) {
-      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
-      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
-      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, y, v); break;
+      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
+      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
+      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
     }
     return hipGetLastError();
   }
   const int key = (y != nullptr ? 2 : 0) | (dx != nullptr ? 1 : 0);
 #define PWL_BB(UU, A, B)                                                                              \
-  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, bl.tables, p.runs, p.run_begin, x, g, \
+  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, p.runs, p.run_begin, x, g, \
                      y, dx, dv, v)
 #define PWL_BB_U(UU)                             \
   switch (key) {                                 \
@@ -166,8 +223,8 @@ hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchCo
 
 hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
                         float* dv, hipStream_t s) {
-  const LaunchConfig c = get_launch(PWL_KERNEL_BATCH);
   const bool backward = g != nullptr;
+  const LaunchConfig c = get_launch(backward ? PWL_KERNEL_BATCH_BACKWARD : PWL_KERNEL_BATCH);
   const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
                    (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const int v = vec ? 1 : 0;
@@ -180,6 +237,12 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
     const hipError_t e = launch_plan(bl, backward ? bl.bwd[k] : bl.fwd[k], c, x, g, y, dx, dv, v, s);
     if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pack(const BatchTable* tabs, int T, int32_t* maxc, hipStream_t s) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_pack, dim3(T), dim3(256), 0, s, tabs, maxc);
   return hipGetLastError();
 }
 

@@ -201,8 +201,8 @@ constexpr int kRowsPerThread = (PWL_MAX_N + 1 + kFinalizeThreads - 1) / kFinaliz
 //     cell(x_0) = -1 and cell(x_N) = K - 1, so each cell is written once when
 //     the knots increase; the knot-collapse check; the deepest cell (the
 //     evaluator's unrolled compare depth);
-//  3. (projection) <f, phi_k> by 16-point Gauss-Legendre per segment, one lane
-//     per (segment, node), reduced across each 16-lane group;
+//  3. (projection) <f, phi_k> by 16-point Gauss-Legendre per segment, one
+//     thread per segment;
 //  4. (projection) the FP64 solve of M c = b by parallel cyclic reduction;
 //  5. the packed records {x_k, v_k, slope_k, 1/h_k} (NaN for a collapsed
 //     table, whose map is then cleared).
@@ -259,28 +259,21 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
 
   // 3-4. vertex values
   if (bp.values == PWL_PROJ) {
-    // lane (k, q): node q of segment k; L_k goes to D[k], R_k to A[k+1]
-    for (int base = 0; base < kGaussPoints * N; base += kFinalizeThreads) {
-      const int gid = base + tid;
-      const int k = gid / kGaussPoints, q = gid % kGaussPoints;
-      float sl = 0.0f, sr = 0.0f, h = 0.0f;
-      if (k < N) {
-        const float xk = X[k];
-        h = X[k + 1] - xk;
+    // one thread per segment k: its 16 Gauss-Legendre nodes in order;
+    // L_k = <f, phi_k> on segment k goes to D[k], R_k = <f, phi_{k+1}> to A[k+1]
+    for (int k = tid; k < N; k += kFinalizeThreads) {
+      const float xk = X[k];
+      const float h = X[k + 1] - xk;
+      float sl = 0.0f, sr = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kGaussPoints; ++q) {
         const float t = bp.gl.t[q];
         const float fq = bp.gl.w[q] * f_value32(bp.f, fmaf(h, t, xk));
-        sl = (1.0f - t) * fq;
-        sr = t * fq;
+        sl = fmaf(1.0f - t, fq, sl);
+        sr = fmaf(t, fq, sr);
       }
-#pragma unroll
-      for (int m = kGaussPoints / 2; m >= 1; m >>= 1) {
-        sl += __shfl_xor(sl, m, kGaussPoints);
-        sr += __shfl_xor(sr, m, kGaussPoints);
-      }
-      if (k < N && q == 0) {
-        D[k] = (double)(h * sl);
-        A[k + 1] = (double)(h * sr);
-      }
+      D[k] = (double)(h * sl);
+      A[k + 1] = (double)(h * sr);
     }
     __syncthreads();
     // Gram matrix of the hat basis from the element matrix (h/6)[[2,1],[1,2]]

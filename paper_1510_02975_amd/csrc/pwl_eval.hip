@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kStreamUnroll = 4;    // float4 vectors per thread per iteration (baselines)
 constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr int kXcds = 8;             // MI355X accelerator complex dies; workgroups go to them round-robin
 
 using namespace stream;
 
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __r
                                                    const float* __restrict__ x,
                                                    const float* __restrict__ g,
                                                    float* __restrict__ y, float* __restrict__ dx,
-                                                   float* __restrict__ dv, int64_t n, int vec) {
+                                                   float* __restrict__ part, int64_t n, int vec) {
   extern __shared__ float4 lds_f4[];
   const Smem s = carve(lds_f4, t.N, t.K, WDV);
   stage_table(t, vo, s);
@@ -76,12 +77,41 @@ __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __r
     default: B::template range<0>(t, s, x, g, y, dx, 0, n, vec != 0, blk, nblk); break;
   }
   if (WDV) {
+    // This workgroup's dL/dv becomes column `col` of the partial sums
+    // part[k][col] (no atomics: k_dv_reduce adds each row in a fixed order).
+    // Workgroups are dealt to the 8 XCDs round-robin, so the columns are
+    // ordered XCD by XCD: the workgroups of one XCD fill whole cache lines
+    // in their own L2.
     __syncthreads();
-    for (int k = threadIdx.x; k <= t.N; k += blockDim.x) {
-      const float v = (float)s.dv[k];
-      if (v != 0.0f) unsafeAtomicAdd(dv + k, v);
-    }
+    const int G = gridDim.x, b = blockIdx.x;
+    const int col = (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
+    for (int k = threadIdx.x; k <= t.N; k += blockDim.x) part[(int64_t)k * G + col] = (float)s.dv[k];
   }
+}
+
+// dL/dv[k] = the sum of row k of part[k][0..G), in FP64 and a fixed order:
+// one wave per row, lane l adding columns l, l + 64, ... (coalesced 256-byte
+// loads, all issued before the first add), then a butterfly over the lanes.
+constexpr int kReduceThreads = 256;
+__global__ __launch_bounds__(kReduceThreads) void k_dv_reduce(const float* __restrict__ part, int G, int N1,
+                                                              float* __restrict__ dv) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (kReduceThreads / 64) + (threadIdx.x >> 6);
+  if (k >= N1) return;   // whole waves leave together
+  const float* row = part + (int64_t)k * G;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < G; c += 256) {
+    s0 += (double)row[c];
+    s1 += (double)row[c + 64];
+    s2 += (double)row[c + 128];
+    s3 += (double)row[c + 192];
+  }
+  for (; c < G; c += 64) s0 += (double)row[c];
+  double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (lane == 0) dv[k] = (float)s;
 }
 
 __global__ __launch_bounds__(1024) void k_locate(EvalTable t, const float* __restrict__ x,
@@ -176,12 +206,16 @@ inline bool same_phase(const void* a, const void* b) {
 // `block` threads per CU (fewer if the table's LDS does not allow that
 // many), each thread handling `unroll` float4 vectors per iteration, and
 // never more workgroups than there are vectors.  The defaults are the
-// autotuner's choice on MI355X for 2^28 points (forward and fused backward:
-// four vectors per thread, two 1024-thread workgroups per CU); a shape with
-// only a few resident workgroups per CU streams fastest.  pwl_set_launch
-// overrides them.
-constexpr LaunchConfig kDefaultLaunch[3] = {{4, 1024, 2}, {4, 1024, 2}, {4, 1024, 2}};
-LaunchConfig g_launch[3] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2]};
+// autotuner's choice on MI355X: forward at 2^28 points, four vectors per
+// thread in 1024-thread workgroups; fused backward at 2^26 points, two
+// vectors per thread in 512-thread workgroups (the dL/dv LDS atomics favour
+// a smaller register footprint); grid of two workgroups per CU.  Register
+// use, not the grid, caps residency: the grid size sets how finely the
+// points are dealt out.  The batched kernels stage a table per run and run
+// best with one 1024-thread workgroup per CU, one vector per thread (every
+// table then shares one launch).  pwl_set_launch overrides them.
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 512, 2}, {1, 1024, 1}, {1, 1024, 1}};
+LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 
 LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t n, int num_cu) {
   const int wg_lds = (int)std::max<size_t>(1, kLdsPerCU / std::max<size_t>(lds, 1));
@@ -197,7 +231,7 @@ LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t 
 }  // namespace
 
 hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu) {
-  if (kernel < 0 || kernel > 2) return hipErrorInvalidValue;
+  if (kernel < 0 || kernel > 3) return hipErrorInvalidValue;
   if (unroll == 0 && block == 0 && wg_per_cu == 0) {
     g_launch[kernel] = kDefaultLaunch[kernel];
     return hipSuccess;
@@ -227,11 +261,11 @@ hipError_t launch_eval(const EvalTable& t, const float* vo, const float* x, floa
 
 template <int U>
 void launch_bwd_u(const LaunchShape& ls, int key, const EvalTable& t, const float* vo, const float* x,
-                  const float* g, float* y, float* dx, float* dv, int64_t n, int vec, hipStream_t s) {
+                  const float* g, float* y, float* dx, float* part, int64_t n, int vec, hipStream_t s) {
 #define PWL_BWD_CASE(K, A, B, C)                                                                 \
   case K:                                                                                        \
     hipLaunchKernelGGL((k_eval_bwd<U, A, B, C>), dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, \
-                       x, g, y, dx, dv, n, vec);                                                 \
+                       x, g, y, dx, part, n, vec);                                               \
     break;
   switch (key) {
     PWL_BWD_CASE(1, false, false, true)
@@ -246,21 +280,44 @@ void launch_bwd_u(const LaunchShape& ls, int key, const EvalTable& t, const floa
 #undef PWL_BWD_CASE
 }
 
+LaunchShape backward_shape(const EvalTable& t, const float* x, const float* g, const float* y, const float* dx,
+                           bool wdv, int64_t n, int num_cu) {
+  const bool vec = same_phase(x, g) && same_phase(x, y) && same_phase(x, dx) &&
+                   (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
+  return stream_shape(g_launch[1], eval_lds_bytes(t.N, t.K, wdv), vec ? n / 4 : 0, n, num_cu);
+}
+
+size_t backward_workspace_floats(const EvalTable& t, const float* x, const float* g, const float* y,
+                                 const float* dx, int64_t n, int num_cu) {
+  const LaunchShape ls = backward_shape(t, x, g, y, dx, true, n, num_cu);
+  return (size_t)ls.grid * (size_t)(t.N + 1);
+}
+
 hipError_t launch_eval_backward(const EvalTable& t, const float* vo, const float* x, const float* g,
-                                float* y, float* dx, float* dv, int64_t n, int num_cu, hipStream_t s) {
+                                float* y, float* dx, float* dv, float* part, int64_t n, int num_cu,
+                                hipStream_t s) {
   const bool vec = same_phase(x, g) && same_phase(x, y) && same_phase(x, dx) &&
                    (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const bool wdv = dv != nullptr;
   const LaunchConfig c = g_launch[1];
-  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, wdv), vec ? n / 4 : 0, n, num_cu);
+  const LaunchShape ls = backward_shape(t, x, g, y, dx, wdv, n, num_cu);
   const int key = (y != nullptr ? 4 : 0) | (dx != nullptr ? 2 : 0) | (wdv ? 1 : 0);
   if (key == 0) return hipErrorInvalidValue;
-  if (wdv) hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, s, dv, (int64_t)t.N + 1);
+  if (wdv && n == 0) {   // no points: dL/dv = 0
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, s, dv, (int64_t)t.N + 1);
+    return hipGetLastError();
+  }
+  if (wdv && part == nullptr) return hipErrorInvalidValue;
   const int v = vec ? 1 : 0;
   switch (c.unroll) {
-    case 1: launch_bwd_u<1>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
-    case 2: launch_bwd_u<2>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
-    default: launch_bwd_u<4>(ls, key, t, vo, x, g, y, dx, dv, n, v, s); break;
+    case 1: launch_bwd_u<1>(ls, key, t, vo, x, g, y, dx, part, n, v, s); break;
+    case 2: launch_bwd_u<2>(ls, key, t, vo, x, g, y, dx, part, n, v, s); break;
+    default: launch_bwd_u<4>(ls, key, t, vo, x, g, y, dx, part, n, v, s); break;
+  }
+  if (wdv) {
+    const int n1 = t.N + 1, rows_per_wg = kReduceThreads / 64;
+    hipLaunchKernelGGL(k_dv_reduce, dim3((n1 + rows_per_wg - 1) / rows_per_wg), dim3(kReduceThreads), 0, s,
+                       part, ls.grid, n1, dv);
   }
   return hipGetLastError();
 }

@@ -69,7 +69,7 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
   // records, knots (+ sentinels), u16 map lo[0..K] padded to 4 bytes, [FP64 dL/dv]
   size_t b = sizeof(float4) * (size_t)N + sizeof(float) * (size_t)(N + kKnotPad) +
              sizeof(uint16_t) * (size_t)((K + 2) & ~1);
-  if (backward) b += 8 + sizeof(double) * (size_t)(N + 1);   // 8-byte aligned FP64 dL/dv
+  if (backward) b += 16 + sizeof(double) * (size_t)(N + 1);  // 16-byte aligned FP64 dL/dv
   return b;
 }
 
@@ -99,16 +99,29 @@ hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu);
 LaunchConfig get_launch(int kernel);
 
 // ---- batched evaluation ----------------------------------------------------
-struct BatchTable {          // one table of a batch, as the device sees it
-  EvalTable t;
-  int64_t dv_off;            // first of its N + 1 entries in the concatenated dL/dv
+// A batch copies every table's LDS image (the layout carve() describes:
+// records, NaN-padded knots, index map) into one arena at creation, so a
+// workgroup stages a table with one linear 16-byte copy.
+struct BatchTable {          // one table of a batch, for packing its image
+  EvalTable t;               // the table's own arrays and shape
+  float4* img;               // its LDS image in the batch arena
+  int32_t nvec;              // image size in 16-byte words
+  int32_t pad;
 };
 
-struct BatchRun {            // points [begin, end) of one table, handled by one workgroup
-  int32_t table;
-  int32_t pad;
+// Points [begin, end) of one table, handled by one workgroup, with the
+// table's shape copied in: a workgroup reads nothing else to evaluate it.
+struct BatchRun {
+  const float4* img;
   int64_t begin, end;
+  int64_t dv_off;            // first of the table's N + 1 entries in the concatenated dL/dv
+  int32_t table, nvec, N, K;
+  float a32, b32, scale32;
+  int32_t maxc;              // most knots sharing one map cell (the unrolled compare depth)
 };
+static_assert(sizeof(BatchRun) == 64, "BatchRun is staged in 16-byte words");
+
+constexpr int kRunSlots = 64;   // run descriptors a workgroup holds in LDS at a time
 
 struct BatchPlan {           // the runs of every workgroup of one launch
   BatchRun* runs;            // device
@@ -118,13 +131,18 @@ struct BatchPlan {           // the runs of every workgroup of one launch
   size_t lds;
 };
 
+// LDS of a batched launch for a table of N segments and K cells: the run
+// descriptors, then the table's image (and the FP64 dL/dv).
+inline size_t batch_lds_bytes(int N, int K, bool backward) {
+  return sizeof(BatchRun) * kRunSlots + ((eval_lds_bytes(N, K, backward) + 15) & ~(size_t)15);
+}
+
 // Tables whose LDS footprint allows the configured workgroups per CU form one
 // class; the larger tables form a second class with fewer, bigger
 // workgroups.  Each class is one persistent launch.
 constexpr int kMaxBatchClasses = 2;
 
 struct BatchLaunch {
-  BatchTable* tables;        // device [T]
   BatchPlan fwd[kMaxBatchClasses], bwd[kMaxBatchClasses];
   int32_t nfwd, nbwd;        // launches per call
   int64_t dv_len;            // sum over tables of N + 1
@@ -132,15 +150,21 @@ struct BatchLaunch {
 
 hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
                         float* dv, hipStream_t s);
+// Writes every table's image and its deepest map cell (maxc[T]).
+hipError_t launch_batch_pack(const BatchTable* tabs, int T, int32_t* maxc, hipStream_t s);
 hipError_t configure_batch_kernels(int max_lds);
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s);
 hipError_t launch_eval(const EvalTable& t, const float* v_override, const float* x, float* y,
                        int64_t n, int num_cu, hipStream_t s);
+// The fused backward writes one row of dL/dv partial sums per workgroup into
+// `part` and adds the rows in a second kernel; the rows it needs:
+size_t backward_workspace_floats(const EvalTable& t, const float* x, const float* g, const float* y,
+                                 const float* dx, int64_t n, int num_cu);
 hipError_t launch_eval_backward(const EvalTable& t, const float* v_override, const float* x,
-                                const float* g, float* y, float* dx, float* dv, int64_t n, int num_cu,
-                                hipStream_t s);
+                                const float* g, float* y, float* dx, float* dv, float* part, int64_t n,
+                                int num_cu, hipStream_t s);
 hipError_t launch_locate(const EvalTable& t, const float* x, int32_t* seg, int64_t n, int num_cu,
                          hipStream_t s);
 hipError_t launch_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int fast,

@@ -27,7 +27,7 @@ __device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
   s.knot = reinterpret_cast<float*>(s.rec + N);
   s.lo = reinterpret_cast<uint16_t*>(s.knot + N + kKnotPad);
   s.dv = backward ? reinterpret_cast<double*>(
-                        (reinterpret_cast<uintptr_t>(s.lo + ((K + 2) & ~1)) + 7) & ~(uintptr_t)7)
+                        (reinterpret_cast<uintptr_t>(s.lo + ((K + 2) & ~1)) + 15) & ~(uintptr_t)15)
                   : nullptr;
   return s;
 }

@@ -3,15 +3,22 @@ predictions, for the Lorentzian on [-20, 20] and Bessel J0 on [0, 50] on the
 optimal partition, N in {256, 1024, 4096}, interpolant and projection values.
 
 For each table the GPU builds:
-  * its L2 error (oracle quadrature on the downloaded table) is within the
-    schedule of Results 4-5: 5% of the prediction at N = 256, 1% at
-    N >= 1024, and the projection/interpolant ratio is 1/sqrt(6) within 2%
-    at N >= 1024 (Result 5);
+  * its knots reach the schedule of Results 4-5: the oracle's values on the
+    GPU's own knots have an L2 error (oracle quadrature) within 5% of the
+    prediction at N = 256 and 1% at N >= 1024, and the projection/interpolant
+    ratio is 1/sqrt(6) within 2% at N >= 1024 (Result 5);
+  * its values differ from those oracle values by at most 1e-6 max|f|, and
+    its own L2 error is within the same schedule widened by the L2 norm of
+    that difference (sqrt(d^T M d), M the Gram matrix).  At N = 4096 the
+    method's error approaches FP32 resolution, and the FP32 hat quadrature
+    on the GPU is then visible in the L2 error;
   * the empirical max |y_gpu - f(x)| over 2^27 uniform points (f in FP64 on
     the host) matches the L-infinity prediction (h^2 |f''| / 8 for the
     interpolant, h^2 |f''| / 12 for the projection) within the same
-    schedule, plus the FP32 evaluation slack: storing v and the slope in FP32
-    and one FMA add at most about 4 * 2^-24 max|f|, so 3e-7 max|f| is allowed.
+    schedule, plus the FP32 slack: the vertex values (at most 1e-6 max|f|
+    off, in practice about 1e-7) and the FP32 evaluation (v and the slope
+    stored in FP32 and one FMA: about 4 * 2^-24 max|f|); 3e-7 max|f| is
+    allowed.
 """
 
 import math
@@ -22,7 +29,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import device, fmax_abs, library, say
+from tests.gpu_util import VALUE_TOL, device, fmax_abs, library, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +58,8 @@ def _tol(N):
 @pytest.mark.parametrize("which", ["lorentz", "j0"])
 @pytest.mark.parametrize("N", [256, 1024, 4096])
 def test_error_schedule_gpu_tables(which, N):
-    P = library()
+    import paper_1510_02975_amd as P
+    library()
     dev = device()
     spec = W.LORENTZ if which == "lorentz" else W.BESSEL
     func, p, a, b = spec["func"], spec["params"], spec["a"], spec["b"]
@@ -65,14 +73,24 @@ def test_error_schedule_gpu_tables(which, N):
         t = P.pwl_build(func, p, a, b, N, O.OPTIMAL, vals)
         d = P.pwl_table_download(t)
         X = d["knots"].astype(np.float64)
-        l2[vals] = O.l2_error(func, p, X, d["values64"])
-        r2 = l2[vals] / pe["l2"][(O.OPTIMAL, vals)]
+        pl2 = pe["l2"][(O.OPTIMAL, vals)]
+        v_or = O.proj_values(func, p, X) if vals == O.PROJ else O.interp_values(func, p, X)
+        l2[vals] = O.l2_error(func, p, X, v_or)
+        r_or = l2[vals] / pl2
+        dv = d["values64"] - v_or
+        _, dg, up = O.mass_matrix(X)
+        dnorm = math.sqrt(max(0.0, float(np.sum(dg * dv * dv) + 2.0 * np.sum(up * dv[:-1] * dv[1:]))))
+        r2 = O.l2_error(func, p, X, d["values64"]) / pl2
         y = P.pwl_eval(t, x).cpu().numpy().astype(np.float64)
         emp = float(np.max(np.abs(y - f_h)))
         pinf = pe["linf"][(O.OPTIMAL, vals)]
-        say("  %s N=%d %s: L2 %.4e (x%.4f of predicted), max|y-f| over 2^27 %.4e (x%.4f of predicted)"
-            % (which, N, "proj" if vals else "interp", l2[vals], r2, emp, emp / pinf))
-        assert abs(r2 - 1.0) <= tol, r2
+        say("  %s N=%d %s: L2 x%.4f of predicted (oracle values on these knots x%.4f, value error "
+            "%.2e max|f|, its L2 norm %.3f of predicted); max|y-f| over 2^27 %.3e (x%.3f of predicted)"
+            % (which, N, "proj" if vals else "interp", r2, r_or, np.max(np.abs(dv)) / fmax, dnorm / pl2,
+               emp, emp / pinf))
+        assert abs(r_or - 1.0) <= tol, r_or
+        assert np.max(np.abs(dv)) <= VALUE_TOL * fmax
+        assert abs(r2 - 1.0) <= tol + dnorm / pl2, r2
         assert emp <= (1.0 + tol) * pinf + EVAL_SLACK * fmax
         # 2^27 points sample every segment densely: the maximum is found
         assert emp >= (1.0 - tol) * pinf - EVAL_SLACK * fmax

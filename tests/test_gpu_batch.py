@@ -131,6 +131,13 @@ def test_batch_misaligned_and_degenerate_shapes():
         ref = torch.cat([P.pwl_eval(t, x[0:7]), P.pwl_eval(t, x[7:12345]), P.pwl_eval(u, x[12345:20003])])
         assert torch.equal(y, ref), off
         bt.free()
+    # the batch holds its own copy of the tables: a freed table is not needed
+    t2 = P.pwl_build(O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 700, O.OPTIMAL, O.INTERP)
+    ref = P.pwl_eval(t2, base)
+    bt = P.pwl_batch_create([t2], [0, base.numel()])
+    t2.free()
+    assert torch.equal(P.pwl_batch_eval(bt, base), ref)
+    bt.free()
     # a single table equals pwl_eval; zero points is valid
     bt = P.pwl_batch_create([t], [0, 20011])
     assert torch.equal(P.pwl_batch_eval(bt, base), P.pwl_eval(t, base))
@@ -143,13 +150,23 @@ def test_batch_misaligned_and_degenerate_shapes():
 
 
 def test_batch_two_lds_classes():
-    """N = 4096 tables need more LDS than the default workgroups per CU allow,
-    so they get a launch of their own next to the small tables; both launches
-    match the per-table evaluator bit for bit (y, dx) and dL/dv matches the
-    oracle, with the two classes interleaved in table order."""
+    """With two workgroups per CU, N = 4096 tables need more LDS than that
+    allows, so they get a launch of their own next to the small tables; both
+    launches match the per-table evaluator bit for bit (y, dx) and dL/dv
+    matches the oracle, with the two classes interleaved in table order."""
     import paper_1510_02975_amd as P
     library()
     dev = device()
+    P.pwl_set_launch(P.KERNEL_BATCH, 2, 1024, 2)
+    P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, 2, 1024, 2)
+    try:
+        _two_classes(P, dev)
+    finally:
+        P.pwl_set_launch(P.KERNEL_BATCH, 0, 0, 0)
+        P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, 0, 0, 0)
+
+
+def _two_classes(P, dev):
     big = P.pwl_build(O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, O.PROJ)
     small = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 64, O.UNIFORM, O.INTERP)
     mid = P.pwl_build(O.BESSEL_J0, (1.0,), 0.0, 50.0, 1000, O.OPTIMAL, O.INTERP)
@@ -164,6 +181,7 @@ def test_batch_two_lds_classes():
     one = P.pwl_batch_create([small], [0, 5])
     say("two classes: grid %d (one small class alone: %d), runs %d" % (bt.grid_fwd, one.grid_fwd, bt.runs_fwd))
     assert bt.grid_fwd > one.grid_fwd
+    bt_grid = bt.grid_fwd
     one.free()
     y = P.pwl_batch_eval(bt, xt)
     yb, dxb, dvb = P.pwl_batch_eval_backward(bt, xt, gt)
@@ -185,11 +203,9 @@ def test_batch_two_lds_classes():
     bt.free()
     # with one workgroup per CU every table fits one class
     P.pwl_set_launch(P.KERNEL_BATCH, 4, 1024, 1)
-    try:
-        b1 = P.pwl_batch_create(tabs, offs)
-        assert torch.equal(P.pwl_batch_eval(b1, xt), y)
-        b1.free()
-    finally:
-        P.pwl_set_launch(P.KERNEL_BATCH, 0, 0, 0)
+    b1 = P.pwl_batch_create(tabs, offs)
+    assert b1.grid_fwd < bt_grid
+    assert torch.equal(P.pwl_batch_eval(b1, xt), y)
+    b1.free()
     for t in (big, small, mid):
         t.free()
