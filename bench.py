@@ -109,11 +109,17 @@ class Marks:
         self.ev = []
 
 
-def timed_median(torch, fn, reps=20, warm=30):
-    """Median launch time after `warm` untimed launches (enough sustained load
-    for the GPU to reach its steady clocks)."""
-    for _ in range(warm):
-        fn(0)
+def timed_median(torch, fn, reps=20, warm=30, warm_seconds=0.05):
+    """Median launch time after at least `warm` untimed launches and
+    `warm_seconds` of sustained load (the GPU raises its clocks under load;
+    a short warm-up times the ramp, not the kernel)."""
+    t0 = time.perf_counter()
+    i = 0
+    while i < warm or time.perf_counter() - t0 < warm_seconds:
+        fn(i)
+        i += 1
+        if i % 10 == 0:
+            torch.cuda.synchronize()
     m = Marks(torch, 2 * reps)
     for i in range(reps):
         m.record(2 * i)
@@ -276,7 +282,7 @@ def batch_extra(torch, P, W, dev, args):
     def per_table(i):
         for t, xs, ys in views:
             P.pwl_eval(t, xs, ys)
-    t_per = timed_median(torch, per_table, reps=3, warm=1)
+    t_per = timed_median(torch, per_table, reps=3, warm=1, warm_seconds=0.0)
     table_bytes = sum(28 * s["N"] for s in specs)
     bt.free()
     for t in tabs:
@@ -461,10 +467,24 @@ def main():
         yg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
         dxg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
         dvg = torch.empty(gs["N"] + 1, dtype=torch.float32, device=dev)
-        t_fb = timed_median(torch, lambda i: P.pwl_eval_backward(tg, xg[i % 2], gg[i % 2], yg[i % 2], dxg[i % 2], dvg))
+        fb = lambda i: P.pwl_eval_backward(tg, xg[i % 2], gg[i % 2], yg[i % 2], dxg[i % 2], dvg)
+        # the library default and a few other launch shapes, timed in this run
+        shapes = {}
+        for shape in (None, (2, 512, 2), (2, 512, 4), (2, 256, 4), (4, 1024, 1)):
+            P.pwl_set_launch(P.KERNEL_BACKWARD, *(shape or (0, 0, 0)))
+            key = "x".join(str(v) for v in P.pwl_get_launch(P.KERNEL_BACKWARD))
+            shapes[key] = timed_median(torch, fb)
+        P.pwl_set_launch(P.KERNEL_BACKWARD, 0, 0, 0)
+        default = "x".join(str(v) for v in P.pwl_get_launch(P.KERNEL_BACKWARD))
+        t_fb = shapes[default]
+        best = min(shapes, key=shapes.get)
         extra["fwd_bwd_workload"] = "gauss_optimal_n512_proj, 2^26 points x~N(0,1), g~N(0,1)"
         extra["fwd_bwd_gpoints_s"] = ng / t_fb / 1e9
         extra["fwd_bwd_hbm_frac"] = FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS
+        extra["fwd_bwd_launch"] = default
+        extra["fwd_bwd_best_launch"] = best
+        extra["fwd_bwd_best_gpoints_s"] = ng / shapes[best] / 1e9
+        extra["fwd_bwd_us_by_launch"] = {k: v * 1e6 for k, v in shapes.items()}
         del xg, gg, yg, dxg
         tg.free()
         log("extras: Lorentzian and J0 tables, 2^27 points")

@@ -207,14 +207,14 @@ inline bool same_phase(const void* a, const void* b) {
 // many), each thread handling `unroll` float4 vectors per iteration, and
 // never more workgroups than there are vectors.  The defaults are the
 // autotuner's choice on MI355X: forward at 2^28 points, four vectors per
-// thread in 1024-thread workgroups; fused backward at 2^26 points, two
-// vectors per thread in 512-thread workgroups (the dL/dv LDS atomics favour
-// a smaller register footprint); grid of two workgroups per CU.  Register
-// use, not the grid, caps residency: the grid size sets how finely the
-// points are dealt out.  The batched kernels stage a table per run and run
+// thread in 1024-thread workgroups, a grid of two workgroups per CU;
+// fused backward at 2^26 points, two vectors per thread (the dL/dv LDS
+// atomics favour a smaller register footprint) in one 768-thread workgroup
+// per CU.  Register use, not the grid, caps residency: the grid size sets
+// how finely the points are dealt out.  The batched kernels stage a table per run and run
 // best with one 1024-thread workgroup per CU, one vector per thread (every
 // table then shares one launch).  pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 512, 2}, {1, 1024, 1}, {1, 1024, 1}};
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 768, 1}, {1, 1024, 1}, {1, 1024, 1}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 
 LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t n, int num_cu) {
