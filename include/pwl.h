@@ -77,6 +77,12 @@ typedef enum pwl_values {
     PWL_PROJ = 1       /* L2 orthogonal projection: M c = b, hat basis (Sec. II-B2)     */
 } pwl_values;
 
+/* Error norms of pwl_plan_tol / pwl_build_tol. */
+typedef enum pwl_norm {
+    PWL_NORM_L2 = 0,    /* || f - v ||_{L2[a,b]}   */
+    PWL_NORM_LINF = 1   /* max over [a, b] |f - v| */
+} pwl_norm;
+
 /* Flags reported by pwl_table_check. */
 #define PWL_FLAG_DEGENERATE 1       /* f'' == 0 everywhere: optimal partition fell back to uniform */
 #define PWL_FLAG_KNOTS_COLLAPSED 2  /* FP32 knots not strictly increasing: table unusable (NaN)    */
@@ -112,6 +118,39 @@ typedef struct pwl_batch pwl_batch;
  */
 pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b,
                      int32_t N, int32_t partition, int32_t values, void* stream, pwl_table** out);
+
+/*
+ * pwl_plan_tol - the number of segments N and the partition that reach a
+ * target error `tol` in `norm` for the given values kind, from the error
+ * predictions the paper derives for smooth f (Sec. III-B2): with
+ * I = int |f''|^(2/5) over [a, b],
+ *   L2, interpolant:  optimal I^(5/2) / (N^2 sqrt(120))             (Result 4)
+ *                     uniform (b-a)^2 ||f''||_2 / (N^2 sqrt(120))    (Result 6)
+ *   L2, projection:   the same divided by sqrt(6)                     (Result 5)
+ *   L-infinity (not in the paper; from the interpolation remainder and the
+ *   projection's element minimisers): optimal max|f''|^(1/5) I^2 / (k N^2),
+ *   uniform (b-a)^2 max|f''| / (k N^2), k = 8 (interpolant), 12 (projection).
+ * The integrals are computed on the GPU (FP64, trapezoid rule on 2^20
+ * cells).  N is the smallest integer whose prediction is <= tol for either
+ * partition; the optimal partition is chosen only when it needs fewer
+ * segments.  These are asymptotic estimates (within a few percent once the
+ * segments resolve f''; N >= 256 for the functions here; the projection's
+ * L-infinity error runs up to ~10% above its estimate), and they describe
+ * the exact CPWL: the FP32 table adds ~1e-7 max|f| (the projection's FP32
+ * quadrature up to ~2e-7), so targets near 1e-6 max|f| and below are met
+ * only up to that floor.  Outputs are
+ * nullable: N, the partition, the predicted error at that N.  Synchronises
+ * `stream`; allocates and frees a small device buffer.  Returns
+ * PWL_ECAPACITY (message: the N needed) when N would exceed PWL_MAX_N, and
+ * N = 1 with a predicted error of 0 when f'' vanishes (affine f).
+ */
+pwl_status pwl_plan_tol(int32_t func, const double* params, int32_t nparams, double a, double b, double tol,
+                        int32_t norm, int32_t values, void* stream, int32_t* N, int32_t* partition,
+                        double* predicted);
+
+/* pwl_build_tol - pwl_plan_tol, then pwl_build with the N and partition it chose. */
+pwl_status pwl_build_tol(int32_t func, const double* params, int32_t nparams, double a, double b, double tol,
+                         int32_t norm, int32_t values, void* stream, pwl_table** out);
 
 /*
  * pwl_rebuild - enqueue a new construction into an existing table, reusing

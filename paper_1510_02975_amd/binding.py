@@ -18,6 +18,7 @@ GAUSSIAN, LORENTZIAN, BESSEL_J0, POLY, EXP = 0, 1, 2, 16, 17
 UNIFORM, OPTIMAL = 0, 1
 INTERP, PROJ = 0, 1
 FLAG_DEGENERATE, FLAG_KNOTS_COLLAPSED, FLAG_NONFINITE = 1, 2, 4
+NORM_L2, NORM_LINF = 0, 1
 MAX_N = 4096
 
 STATUS = {0: "PWL_OK", -1: "PWL_EINVAL", -2: "PWL_ENOMEM", -3: "PWL_EHIP", -4: "PWL_EKNOTS",
@@ -44,6 +45,10 @@ _SIGNATURES = {
                              _c_int32, _c_int32, _vp, ctypes.POINTER(_vp)]),
     "pwl_rebuild": (_c_int32, [_vp, _c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double,
                                _c_int32, _c_int32, _vp]),
+    "pwl_plan_tol": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                _c_int32, _c_int32, _vp, _ip, _ip, _dp]),
+    "pwl_build_tol": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 _c_int32, _c_int32, _vp, ctypes.POINTER(_vp)]),
     "pwl_table_check": (_c_int32, [_vp, _vp, _ip]),
     "pwl_table_info": (_c_int32, [_vp, _ip, _dp, _dp, _ip, _ip, _ip]),
     "pwl_table_download": (_c_int32, [_vp, _fp, _fp, _dp, _dp, _vp]),
@@ -167,6 +172,30 @@ def pwl_build(func, params, a, b, N, partition=OPTIMAL, values=PROJ, stream=None
     _check(lib.pwl_build(int(func), arr, npar, float(a), float(b), int(N), int(partition), int(values),
                          _stream(stream), ctypes.byref(out)))
     t = Table(out, func, params, a, b, int(N), partition, values)
+    if check:
+        pwl_table_check(t, stream)
+    return t
+
+
+def pwl_plan_tol(func, params, a, b, tol, norm=NORM_L2, values=PROJ, stream=None):
+    """(N, partition, predicted error) that reach `tol` in `norm`."""
+    lib = load_library()
+    arr, npar = _params(params)
+    N, part, pred = _c_int32(), _c_int32(), ctypes.c_double()
+    _check(lib.pwl_plan_tol(int(func), arr, npar, float(a), float(b), float(tol), int(norm), int(values),
+                            _stream(stream), ctypes.byref(N), ctypes.byref(part), ctypes.byref(pred)))
+    return N.value, part.value, pred.value
+
+
+def pwl_build_tol(func, params, a, b, tol, norm=NORM_L2, values=PROJ, stream=None, check=True):
+    """Build the table pwl_plan_tol chooses; returns a Table."""
+    N, part, _ = pwl_plan_tol(func, params, a, b, tol, norm, values, stream)
+    lib = load_library()
+    arr, npar = _params(params)
+    out = ctypes.c_void_p()
+    _check(lib.pwl_build_tol(int(func), arr, npar, float(a), float(b), float(tol), int(norm), int(values),
+                             _stream(stream), ctypes.byref(out)))
+    t = Table(out, func, params, a, b, N, part, values)
     if check:
         pwl_table_check(t, stream)
     return t

@@ -291,6 +291,81 @@ pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double
   return PWL_OK;
 }
 
+namespace {
+
+// Fine cells for the prediction integrals: the density has |x - z|^(2/5)
+// cusps at zeros of f'', so the trapezoid rule converges as dt^(7/5); 2^20
+// cells give ~1e-8 relative accuracy, far below what moves N.
+constexpr int kNormCells = 1 << 20;
+
+}  // namespace
+
+pwl_status pwl_plan_tol(int32_t func, const double* params, int32_t nparams, double a, double b, double tol,
+                        int32_t norm, int32_t values, void* stream, int32_t* N_out, int32_t* partition_out,
+                        double* predicted_out) {
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(PWL_EINVAL, "tol must be finite and > 0");
+  if (norm != PWL_NORM_L2 && norm != PWL_NORM_LINF) return fail(PWL_EINVAL, "unknown norm %d", norm);
+  pwl::BuildParams bp;
+  pwl_status st = resolve_build(func, params, nparams, a, b, 1, PWL_UNIFORM, values, &bp);
+  if (st != PWL_OK) return st;
+  int dev = 0;
+  st = device_ready(&dev, nullptr);
+  if (st != PWL_OK) return st;
+  const int G = pwl::norm_blocks(kNormCells);
+  void* scratch = nullptr;
+  hipError_t e = hipMalloc(&scratch, sizeof(double) * (3 * (size_t)G + 3));
+  if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc for the prediction integrals failed: %s", hipGetErrorString(e));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double h[3] = {0.0, 0.0, 0.0};
+  e = pwl::launch_norms(bp.f, bp.a, bp.b, kNormCells, static_cast<double*>(scratch), s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h, static_cast<double*>(scratch) + 3 * G, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return fail(PWL_EHIP, "prediction integrals failed: %s", hipGetErrorString(e));
+  const double I25 = h[0], l2f2 = std::sqrt(h[1]), maxf2 = h[2], L = bp.b - bp.a;
+  if (!std::isfinite(I25) || !std::isfinite(l2f2) || !std::isfinite(maxf2))
+    return fail(PWL_EINVAL, "the second derivative is not finite on [a, b]");
+  // predicted error = C / N^2 (Results 4-6, Sec. III-B2; L-infinity from the
+  // interpolation remainder h^2 |f''| / 8 and the projection's h^2 |f''| / 12)
+  const double r120 = std::sqrt(120.0), r6 = std::sqrt(6.0);
+  double c_opt, c_uni;
+  if (norm == PWL_NORM_L2) {
+    c_opt = std::pow(I25, 2.5) / r120;
+    c_uni = L * L * l2f2 / r120;
+    if (values == PWL_PROJ) {
+      c_opt /= r6;
+      c_uni /= r6;
+    }
+  } else {
+    const double k = (values == PWL_PROJ) ? 12.0 : 8.0;
+    c_opt = std::pow(maxf2, 0.2) * I25 * I25 / k;
+    c_uni = L * L * maxf2 / k;
+  }
+  auto need = [&](double c) -> double { return (c > 0.0) ? std::ceil(std::sqrt(c / tol)) : 1.0; };
+  const double n_opt = std::max(1.0, need(c_opt)), n_uni = std::max(1.0, need(c_uni));
+  // the optimal partition only when it needs fewer segments (its build costs more)
+  const bool opt = n_opt < n_uni;
+  const double n = opt ? n_opt : n_uni, c = opt ? c_opt : c_uni;
+  if (n > PWL_MAX_N)
+    return fail(PWL_ECAPACITY, "tol = %g needs N = %.0f segments (PWL_MAX_N = %d; the best at N = %d is %g)",
+                tol, n, PWL_MAX_N, PWL_MAX_N, c / ((double)PWL_MAX_N * PWL_MAX_N));
+  if (N_out) *N_out = (int32_t)n;
+  if (partition_out) *partition_out = opt ? PWL_OPTIMAL : PWL_UNIFORM;
+  if (predicted_out) *predicted_out = c / (n * n);
+  return PWL_OK;
+}
+
+pwl_status pwl_build_tol(int32_t func, const double* params, int32_t nparams, double a, double b, double tol,
+                         int32_t norm, int32_t values, void* stream, pwl_table** out) {
+  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
+  *out = nullptr;
+  int32_t N = 0, partition = 0;
+  pwl_status st = pwl_plan_tol(func, params, nparams, a, b, tol, norm, values, stream, &N, &partition, nullptr);
+  if (st != PWL_OK) return st;
+  return pwl_build(func, params, nparams, a, b, N, partition, values, stream, out);
+}
+
 pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t nparams, double a,
                        double b, int32_t partition, int32_t values, void* stream) {
   if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");

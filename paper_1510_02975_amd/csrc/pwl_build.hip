@@ -374,7 +374,71 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
   }
 }
 
+// ---- error-prediction integrals (choice of N for a target error) ----------
+constexpr int kNormThreads = 1024;
+
+// Block b of the fine grid t_j = a + j (b - a) / Q, j = 0..Q: trapezoid
+// weights times |f''|^(2/5) and f''^2, and max |f''|, reduced in FP64 in a
+// fixed order (a tree over the block's threads).
+__global__ __launch_bounds__(kNormThreads) void k_norms(FuncDesc f, double a, double b, int Q,
+                                                        double* __restrict__ part) {
+  __shared__ double s_d[kNormThreads], s_q[kNormThreads], s_m[kNormThreads];
+  const int tid = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * kNormThreads + tid;
+  const double dt = (b - a) / (double)Q;
+  double d = 0.0, q = 0.0, m = 0.0;
+  if (j <= Q) {
+    const double x = a + (double)j * dt;
+    const double f2 = f_second64(f, x);
+    const double w = (j == 0 || j == Q) ? 0.5 * dt : dt;
+    d = w * knot_density(f, x);
+    q = w * f2 * f2;
+    m = fabs(f2);
+  }
+  s_d[tid] = d;
+  s_q[tid] = q;
+  s_m[tid] = m;
+  __syncthreads();
+  for (int h = kNormThreads / 2; h >= 1; h >>= 1) {
+    if (tid < h) {
+      s_d[tid] += s_d[tid + h];
+      s_q[tid] += s_q[tid + h];
+      s_m[tid] = fmax(s_m[tid], s_m[tid + h]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[3 * blockIdx.x] = s_d[0];
+    part[3 * blockIdx.x + 1] = s_q[0];
+    part[3 * blockIdx.x + 2] = s_m[0];
+  }
+}
+
+// One thread adds the G block results in order: out = {int |f''|^(2/5),
+// int f''^2, max |f''|}.
+__global__ void k_norms_final(const double* __restrict__ part, int G, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double d = 0.0, q = 0.0, m = 0.0;
+  for (int g = 0; g < G; ++g) {
+    d += part[3 * g];
+    q += part[3 * g + 1];
+    m = fmax(m, part[3 * g + 2]);
+  }
+  out[0] = d;
+  out[1] = q;
+  out[2] = m;
+}
+
 }  // namespace
+
+int norm_blocks(int Q) { return Q / kNormThreads + 1; }
+
+hipError_t launch_norms(const FuncDesc& f, double a, double b, int Q, double* scratch, hipStream_t s) {
+  const int G = norm_blocks(Q);
+  hipLaunchKernelGGL(k_norms, dim3(G), dim3(kNormThreads), 0, s, f, a, b, Q, scratch);
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(64), 0, s, scratch, G, scratch + 3 * G);
+  return hipGetLastError();
+}
 
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s) {
   if (bp.partition == PWL_OPTIMAL) {

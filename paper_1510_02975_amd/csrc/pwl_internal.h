@@ -156,6 +156,11 @@ hipError_t configure_batch_kernels(int max_lds);
 
 // ---- launchers (defined in the .hip files) --------------------------------
 hipError_t launch_build(const BuildParams& bp, const TableDev& td, hipStream_t s);
+// The integrals behind the error predictions, on Q trapezoid cells of [a, b]:
+// scratch holds 3 * norm_blocks(Q) partial sums, then {int |f''|^(2/5),
+// int f''^2, max |f''|}.
+int norm_blocks(int Q);
+hipError_t launch_norms(const FuncDesc& f, double a, double b, int Q, double* scratch, hipStream_t s);
 hipError_t launch_eval(const EvalTable& t, const float* v_override, const float* x, float* y,
                        int64_t n, int num_cu, hipStream_t s);
 // The fused backward writes one row of dL/dv partial sums per workgroup into

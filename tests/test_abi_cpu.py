@@ -146,3 +146,24 @@ def test_set_launch_validation():
     assert lib.pwl_set_launch(0, 0, 0, 0) == 0            # defaults back
     lib.pwl_get_launch(0, ctypes.byref(u2), None, None)
     assert u2.value == u.value
+
+
+def test_plan_tol_rejects_invalid_arguments_on_host():
+    lib = library()
+    n, part, pred = ctypes.c_int32(-7), ctypes.c_int32(-7), ctypes.c_double(-1.0)
+    p = (ctypes.c_double * 2)(1.0, 1.0)
+    args = lambda tol, norm, vals, a=-5.0, b=5.0, func=0: lib.pwl_plan_tol(
+        func, p, 2, a, b, tol, norm, vals, None, ctypes.byref(n), ctypes.byref(part), ctypes.byref(pred))
+    assert args(0.0, 0, 1) == -1                  # tol must be > 0
+    assert args(-1e-3, 0, 1) == -1
+    assert args(float("nan"), 0, 1) == -1
+    assert args(float("inf"), 0, 1) == -1
+    assert args(1e-3, 2, 1) == -1                 # unknown norm
+    assert args(1e-3, 0, 5) == -1                 # unknown values kind
+    assert args(1e-3, 0, 1, a=1.0, b=1.0) == -1   # empty domain
+    assert args(1e-3, 0, 1, func=99) == -1        # unknown function
+    assert n.value == -7 and part.value == -7 and pred.value == -1.0
+    out = ctypes.c_void_p(5)
+    assert lib.pwl_build_tol(0, p, 2, -5.0, 5.0, 0.0, 0, 1, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert lib.pwl_build_tol(0, p, 2, -5.0, 5.0, 1e-3, 0, 1, None, None) == -1
