@@ -454,7 +454,13 @@ def main():
     t_copy = timed_median(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % sets]))
     extra["copy_GBs"] = 8.0 * n / t_copy / 1e9
     if not args.no_extra:
-        log("extras: direct expf, fused forward+backward")
+        log("extras: binary-search locate, direct expf, fused forward+backward")
+        # the paper's own locate (binary search over the knots) on the same table and points
+        P.pwl_set_locate(P.LOCATE_SEARCH)
+        t_bs = timed_median(torch, lambda i: P.pwl_eval(tables[0], xs[i % sets], ys[i % sets]))
+        P.pwl_set_locate(P.LOCATE_MAP)
+        extra["locate_search_eval_us"] = t_bs * 1e6
+        extra["locate_search_gpoints_s"] = n / t_bs / 1e9
         for fast in (0, 1):
             t = timed_median(torch, lambda i: P.pwl_direct_gaussian(xs[i % sets], ys[i % sets], 1.0, 1.0, fast))
             extra["direct_%s_gpoints_s" % ("fast_expf" if fast else "expf")] = n / t / 1e9

@@ -315,6 +315,20 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream);
 pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t wg_per_cu);
 pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32_t* wg_per_cu);
 
+#define PWL_LOCATE_MAP 0      /* uniform index map + unrolled compares (default)              */
+#define PWL_LOCATE_SEARCH 1   /* branch-free binary search over the knots in LDS (Sec. IV-V)  */
+
+/*
+ * pwl_set_locate - process-wide segment locate of pwl_eval (step 1 of
+ * Algorithm 1): the index map, or the paper's own GPU technique, a binary
+ * search unrolled into selects, over the knots staged in LDS (no map).
+ * Both give the same segment, so the outputs are bit-identical; the choice
+ * is a speed A/B.  Takes effect for later launches.  pwl_get_locate reads
+ * the mode back.
+ */
+pwl_status pwl_set_locate(int32_t mode);
+int32_t pwl_get_locate(void);
+
 /* ---- library ------------------------------------------------------------ */
 
 const char* pwl_last_error(void);

@@ -68,6 +68,8 @@ _SIGNATURES = {
     "pwl_batch_free": (None, [_vp]),
     "pwl_set_launch": (_c_int32, [_c_int32, _c_int32, _c_int32, _c_int32]),
     "pwl_get_launch": (_c_int32, [_c_int32, _ip, _ip, _ip]),
+    "pwl_set_locate": (_c_int32, [_c_int32]),
+    "pwl_get_locate": (_c_int32, []),
     "pwl_last_error": (ctypes.c_char_p, []),
     "pwl_abi_version": (_c_int32, []),
 }
@@ -394,6 +396,17 @@ def pwl_get_launch(kernel):
     u, b, w = _c_int32(), _c_int32(), _c_int32()
     _check(load_library().pwl_get_launch(int(kernel), ctypes.byref(u), ctypes.byref(b), ctypes.byref(w)))
     return u.value, b.value, w.value
+
+
+LOCATE_MAP, LOCATE_SEARCH = 0, 1
+
+
+def pwl_set_locate(mode):
+    _check(load_library().pwl_set_locate(int(mode)))
+
+
+def pwl_get_locate():
+    return int(load_library().pwl_get_locate())
 
 
 def pwl_last_error():

@@ -38,19 +38,24 @@ using namespace stream;
 template <int U>
 __global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __restrict__ vo,
                                                    const float* __restrict__ x,
-                                                   float* __restrict__ y, int64_t n, int vec) {
+                                                   float* __restrict__ y, int64_t n, int flags) {
   extern __shared__ float4 lds_f4[];
   const Smem s = carve(lds_f4, t.N, t.K, false);
   stage_table(t, vo, s);
   __syncthreads();
   const int64_t blk = blockIdx.x, nblk = gridDim.x;
+  const bool vec = (flags & 1) != 0;
+  if (flags & 2) {   // PWL_LOCATE_SEARCH
+    fwd_range<U, -1>(t, s, x, y, 0, n, vec, blk, nblk);
+    return;
+  }
   switch (t.meta[1]) {
     case 0:
-    case 1: fwd_range<U, 1>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
-    case 2: fwd_range<U, 2>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
-    case 3: fwd_range<U, 3>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
-    case 4: fwd_range<U, 4>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
-    default: fwd_range<U, 0>(t, s, x, y, 0, n, vec != 0, blk, nblk); break;
+    case 1: fwd_range<U, 1>(t, s, x, y, 0, n, vec, blk, nblk); break;
+    case 2: fwd_range<U, 2>(t, s, x, y, 0, n, vec, blk, nblk); break;
+    case 3: fwd_range<U, 3>(t, s, x, y, 0, n, vec, blk, nblk); break;
+    case 4: fwd_range<U, 4>(t, s, x, y, 0, n, vec, blk, nblk); break;
+    default: fwd_range<U, 0>(t, s, x, y, 0, n, vec, blk, nblk); break;
   }
 }
 
@@ -216,6 +221,7 @@ inline bool same_phase(const void* a, const void* b) {
 // table then shares one launch).  pwl_set_launch overrides them.
 constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 768, 1}, {1, 1024, 1}, {1, 1024, 1}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
+int g_locate = PWL_LOCATE_MAP;
 
 LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t n, int num_cu) {
   const int wg_lds = (int)std::max<size_t>(1, kLdsPerCU / std::max<size_t>(lds, 1));
@@ -245,12 +251,20 @@ hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu) {
 
 LaunchConfig get_launch(int kernel) { return g_launch[kernel]; }
 
+hipError_t set_locate(int mode) {
+  if (mode != PWL_LOCATE_MAP && mode != PWL_LOCATE_SEARCH) return hipErrorInvalidValue;
+  g_locate = mode;
+  return hipSuccess;
+}
+
+int get_locate() { return g_locate; }
+
 hipError_t launch_eval(const EvalTable& t, const float* vo, const float* x, float* y, int64_t n,
                        int num_cu, hipStream_t s) {
   const bool vec = same_phase(x, y) && (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const LaunchConfig c = g_launch[0];
   const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, false), vec ? n / 4 : 0, n, num_cu);
-  const int v = vec ? 1 : 0;
+  const int v = (vec ? 1 : 0) | (g_locate == PWL_LOCATE_SEARCH ? 2 : 0);
   switch (c.unroll) {
     case 1: hipLaunchKernelGGL(k_eval_fwd<1>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
     case 2: hipLaunchKernelGGL(k_eval_fwd<2>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;

@@ -97,6 +97,8 @@ struct LaunchConfig {
 
 hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu);
 LaunchConfig get_launch(int kernel);
+hipError_t set_locate(int mode);
+int get_locate();
 
 // ---- batched evaluation ----------------------------------------------------
 // A batch copies every table's LDS image (the layout carve() describes:

@@ -82,9 +82,25 @@ __device__ __forceinline__ int locate_any(float x, const EvalTable& t, const Sme
   return seg;
 }
 
+// The paper's GPU locate (Sec. IV-V): a branch-free binary search over the
+// knots, here the interior knots in LDS.  It counts the interior knots <= x
+// (so x_i <= x < x_{i+1}; NaN x compares false and gives 0), halving a
+// power-of-two step from the largest one below N.
+__device__ __forceinline__ int locate_search(float x, const EvalTable& t, const Smem& s) {
+  int lo = 0;
+  for (int half = (t.N > 1) ? (1 << (31 - __builtin_clz(t.N - 1))) : 0; half >= 1; half >>= 1) {
+    const int k = lo + half;
+    lo = (k < t.N && s.knot[k] <= x) ? k : lo;
+  }
+  return lo;
+}
+
+// MAXC > 0: map + MAXC unrolled compares; 0: map + counted compares;
+// -1: binary search without the map.
 template <int MAXC>
 __device__ __forceinline__ int locate(float x, const EvalTable& t, const Smem& s) {
   if (MAXC > 0) return locate_fixed<MAXC>(x, t, s);
+  if (MAXC < 0) return locate_search(x, t, s);
   return locate_any(x, t, s);
 }
 

@@ -167,3 +167,12 @@ def test_plan_tol_rejects_invalid_arguments_on_host():
     assert lib.pwl_build_tol(0, p, 2, -5.0, 5.0, 0.0, 0, 1, None, ctypes.byref(out)) == -1
     assert out.value is None
     assert lib.pwl_build_tol(0, p, 2, -5.0, 5.0, 1e-3, 0, 1, None, None) == -1
+
+
+def test_set_locate_validation():
+    lib = library()
+    assert lib.pwl_set_locate(7) == -1
+    assert lib.pwl_set_locate(-1) == -1
+    assert lib.pwl_get_locate() == 0
+    assert lib.pwl_set_locate(1) == 0 and lib.pwl_get_locate() == 1
+    assert lib.pwl_set_locate(0) == 0 and lib.pwl_get_locate() == 0
