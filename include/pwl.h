@@ -64,7 +64,8 @@ typedef enum pwl_func {
     PWL_F_LORENTZIAN = 1,  /* amp / (1 + (x / g)^2);      params {g [1], amp [1]}, g > 0   (Sec. VI-B) */
     PWL_F_BESSEL_J0 = 2,   /* amp * J0(x);                params {amp [1]}                 (Sec. VI-C) */
     PWL_F_POLY = 16,       /* c0 + c1 x + ... + c5 x^5;   params {c0 .. c5} (test function)           */
-    PWL_F_EXP = 17         /* amp * exp(alpha x);         params {alpha [1], amp [1]} (test function)  */
+    PWL_F_EXP = 17,        /* amp * exp(alpha x);         params {alpha [1], amp [1]} (test function)  */
+    PWL_F_SAMPLED = 32     /* given by samples: pwl_build_sampled only                                 */
 } pwl_func;
 
 typedef enum pwl_partition {
@@ -118,6 +119,23 @@ typedef struct pwl_batch pwl_batch;
  */
 pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b,
                      int32_t N, int32_t partition, int32_t values, void* stream, pwl_table** out);
+
+/*
+ * pwl_build_sampled - a table for any f given by samples: f_i = f(t_i) and
+ * f2_i = f''(t_i) at t_i = a + i (b - a) / S, i = 0..S (DEVICE FP64 arrays of
+ * S + 1 values, S >= 1).  Between samples f is the cubic spline with those
+ * values and second derivatives (on [t_i, t_{i+1}], u = (x - t_i) / h:
+ * (1-u) f_i + u f_{i+1} - h^2 u (1-u) ((2-u) f2_i + (1+u) f2_{i+1}) / 6), so
+ * f'' is the linear interpolant of f2 - the density of the optimal
+ * partition (Sec. III-B1) and the values follow as for the built-in
+ * functions.  The other arguments are as in pwl_build (the table domain is
+ * [a, b] rounded to FP32).  The build enqueued on `stream` reads the
+ * samples: keep them alive until it has run (pwl_table_check synchronises).
+ * A sampled table cannot be rebuilt with pwl_rebuild (PWL_EINVAL): build a
+ * new one.
+ */
+pwl_status pwl_build_sampled(const double* f, const double* f2, int32_t S, double a, double b, int32_t N,
+                             int32_t partition, int32_t values, void* stream, pwl_table** out);
 
 /*
  * pwl_plan_tol - the number of segments N and the partition that reach a

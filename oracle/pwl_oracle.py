@@ -34,6 +34,7 @@ notes of the repository):
     NaN y and NaN dL/dx and adds nothing to dL/dv.
 """
 
+import collections
 import math
 
 import numpy as np
@@ -45,6 +46,13 @@ LORENTZIAN = 1   # amp / (1 + (x / g)^2);      params (g, amp)
 BESSEL_J0 = 2    # amp * J0(x);                params (amp,)
 POLY = 16        # sum_k c_k x^k, degree <= 5; params (c0, ..., c5)
 EXP = 17         # amp * exp(alpha x);         params (alpha, amp)
+SAMPLED = 32     # any f given by samples;     params Samples(f, f2, a, b)
+
+# f_i = f(t_i) and f2_i = f''(t_i) at t_i = a + i (b - a) / S, i = 0..S.
+# Between samples f is the cubic spline with these values and second
+# derivatives (the standard representation of a cubic spline by its moments),
+# so f'' is the linear interpolant of f2.
+Samples = collections.namedtuple("Samples", "f f2 a b")
 
 UNIFORM, OPTIMAL = 0, 1
 INTERP, PROJ = 0, 1
@@ -60,6 +68,10 @@ class KnotCollapse(ValueError):
 
 
 def _default_params(func, params):
+    if func == SAMPLED:
+        if not isinstance(params, Samples):
+            raise ValueError("a sampled function takes a Samples(f, f2, a, b)")
+        return params
     if params is None or len(params) == 0:
         return {GAUSSIAN: (1.0, 1.0), LORENTZIAN: (1.0, 1.0), BESSEL_J0: (1.0,),
                 POLY: (0.0,), EXP: (1.0, 1.0)}[func]
@@ -77,9 +89,36 @@ def fl32(x):
 # normalisation constants of the paper are folded into `amp`.
 # ---------------------------------------------------------------------------
 
+def _sample_cell(smp, x):
+    """Interval i (end intervals extended) and local coordinate u of x."""
+    S = len(smp.f) - 1
+    h = (smp.b - smp.a) / S
+    s = (x - smp.a) / h
+    i = np.clip(np.floor(s), 0, S - 1).astype(np.int64)
+    return i, s - i, h
+
+
+def _spline_value(smp, x):
+    """On [t_i, t_{i+1}] with u = (x - t_i) / h, the cubic whose values are
+    f_i, f_{i+1} and whose second derivatives are f2_i, f2_{i+1}:
+    (1-u) f_i + u f_{i+1} - h^2 u (1-u) ((2-u) f2_i + (1+u) f2_{i+1}) / 6."""
+    f, f2 = np.asarray(smp.f, np.float64), np.asarray(smp.f2, np.float64)
+    i, u, h = _sample_cell(smp, x)
+    return ((1.0 - u) * f[i] + u * f[i + 1]
+            - h * h * u * (1.0 - u) * ((2.0 - u) * f2[i] + (1.0 + u) * f2[i + 1]) / 6.0)
+
+
+def _spline_second(smp, x):
+    f2 = np.asarray(smp.f2, np.float64)
+    i, u, _ = _sample_cell(smp, x)
+    return (1.0 - u) * f2[i] + u * f2[i + 1]
+
+
 def f_value(func, params, x):
     p = _default_params(func, params)
     x = np.asarray(x, dtype=np.float64)
+    if func == SAMPLED:
+        return _spline_value(p, x)
     if func == GAUSSIAN:
         s, amp = p[0], (p[1] if len(p) > 1 else 1.0)
         return amp * np.exp(-(x * x) / (2.0 * s * s))
@@ -102,6 +141,8 @@ def f_second(func, params, x):
     """f''(x), written from calculus (independent of any finite difference)."""
     p = _default_params(func, params)
     x = np.asarray(x, dtype=np.float64)
+    if func == SAMPLED:
+        return _spline_second(p, x)
     if func == GAUSSIAN:
         s, amp = p[0], (p[1] if len(p) > 1 else 1.0)
         return amp * ((x * x) / s ** 4 - 1.0 / (s * s)) * np.exp(-(x * x) / (2.0 * s * s))

@@ -14,7 +14,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpwl.so")
 
-GAUSSIAN, LORENTZIAN, BESSEL_J0, POLY, EXP = 0, 1, 2, 16, 17
+GAUSSIAN, LORENTZIAN, BESSEL_J0, POLY, EXP, SAMPLED = 0, 1, 2, 16, 17, 32
 UNIFORM, OPTIMAL = 0, 1
 INTERP, PROJ = 0, 1
 FLAG_DEGENERATE, FLAG_KNOTS_COLLAPSED, FLAG_NONFINITE = 1, 2, 4
@@ -45,6 +45,8 @@ _SIGNATURES = {
                              _c_int32, _c_int32, _vp, ctypes.POINTER(_vp)]),
     "pwl_rebuild": (_c_int32, [_vp, _c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double,
                                _c_int32, _c_int32, _vp]),
+    "pwl_build_sampled": (_c_int32, [_vp, _vp, _c_int32, ctypes.c_double, ctypes.c_double, _c_int32, _c_int32,
+                                     _c_int32, _vp, ctypes.POINTER(_vp)]),
     "pwl_plan_tol": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 _c_int32, _c_int32, _vp, _ip, _ip, _dp]),
     "pwl_build_tol": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -174,6 +176,25 @@ def pwl_build(func, params, a, b, N, partition=OPTIMAL, values=PROJ, stream=None
     _check(lib.pwl_build(int(func), arr, npar, float(a), float(b), int(N), int(partition), int(values),
                          _stream(stream), ctypes.byref(out)))
     t = Table(out, func, params, a, b, int(N), partition, values)
+    if check:
+        pwl_table_check(t, stream)
+    return t
+
+
+def pwl_build_sampled(f, f2, a, b, N, partition=OPTIMAL, values=PROJ, stream=None, check=True):
+    """Table for the function sampled as f[i], f2[i] = f(t_i), f''(t_i) at
+    t_i = a + i (b - a) / S (device FP64 tensors of S + 1 values).  With
+    check the stream is synchronised, so the samples may be freed after."""
+    if f.dtype != torch.float64 or f2.dtype != torch.float64:
+        raise TypeError("samples must be float64")
+    if f.numel() != f2.numel() or f.numel() < 2:
+        raise ValueError("f and f2 need the same number (>= 2) of samples")
+    lib = load_library()
+    out = ctypes.c_void_p()
+    _check(lib.pwl_build_sampled(_ptr(f, torch.float64, "f"), _ptr(f2, torch.float64, "f2"), f.numel() - 1,
+                                 float(a), float(b), int(N), int(partition), int(values), _stream(stream),
+                                 ctypes.byref(out)))
+    t = Table(out, SAMPLED, None, a, b, int(N), partition, values)
     if check:
         pwl_table_check(t, stream)
     return t

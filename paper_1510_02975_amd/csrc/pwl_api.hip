@@ -163,6 +163,8 @@ pwl_status resolve_func(int32_t func, const double* params, int32_t nparams, pwl
     case PWL_F_POLY:
       for (int i = 0; i < PWL_MAX_PARAMS; ++i) fd->p[i] = get(i, 0.0);
       break;
+    case PWL_F_SAMPLED:
+      return fail(PWL_EINVAL, "a sampled function is built with pwl_build_sampled");
     case PWL_F_EXP:
       if (nparams > 2) return fail(PWL_EINVAL, "exp takes at most 2 parameters");
       fd->p[0] = get(0, 1.0);
@@ -259,20 +261,17 @@ int32_t pwl_abi_version(void) { return PWL_ABI_VERSION; }
 
 const char* pwl_last_error(void) { return g_err.c_str(); }
 
-pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b, int32_t N,
-                     int32_t partition, int32_t values, void* stream, pwl_table** out) {
-  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
-  *out = nullptr;
-  pwl::BuildParams bp;
-  pwl_status st = resolve_build(func, params, nparams, a, b, N, partition, values, &bp);
-  if (st != PWL_OK) return st;
+namespace {
+
+// Allocates a table for resolved build parameters and enqueues its build.
+pwl_status create_table(const pwl::BuildParams& bp, void* stream, pwl_table** out) {
   int dev = 0, max_lds = 0;
-  st = device_ready(&dev, nullptr, &max_lds);
+  pwl_status st = device_ready(&dev, nullptr, &max_lds);
   if (st != PWL_OK) return st;
   const size_t need = std::max(pwl::finalize_lds_bytes(bp.N),
                                pwl::batch_lds_bytes(bp.N, pwl::map_cells_for(bp.N, PWL_OPTIMAL), true));
   if (need > (size_t)max_lds)
-    return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", N, need, max_lds);
+    return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", bp.N, need, max_lds);
   pwl::TableDev td;
   const int kcap = std::max(pwl::map_cells_for(bp.N, PWL_UNIFORM), pwl::map_cells_for(bp.N, PWL_OPTIMAL));
   const size_t bytes = layout(&td, nullptr, bp.N, kcap, bp.G);
@@ -289,6 +288,18 @@ pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double
   }
   *out = t;
   return PWL_OK;
+}
+
+}  // namespace
+
+pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b, int32_t N,
+                     int32_t partition, int32_t values, void* stream, pwl_table** out) {
+  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
+  *out = nullptr;
+  pwl::BuildParams bp;
+  pwl_status st = resolve_build(func, params, nparams, a, b, N, partition, values, &bp);
+  if (st != PWL_OK) return st;
+  return create_table(bp, stream, out);
 }
 
 namespace {
@@ -364,6 +375,25 @@ pwl_status pwl_build_tol(int32_t func, const double* params, int32_t nparams, do
   pwl_status st = pwl_plan_tol(func, params, nparams, a, b, tol, norm, values, stream, &N, &partition, nullptr);
   if (st != PWL_OK) return st;
   return pwl_build(func, params, nparams, a, b, N, partition, values, stream, out);
+}
+
+pwl_status pwl_build_sampled(const double* f, const double* f2, int32_t S, double a, double b, int32_t N,
+                             int32_t partition, int32_t values, void* stream, pwl_table** out) {
+  if (out == nullptr) return fail(PWL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (f == nullptr || f2 == nullptr) return fail(PWL_EINVAL, "f and f2 must be non-NULL device arrays");
+  if (S < 1) return fail(PWL_EINVAL, "S must be >= 1, got %d", S);
+  // resolve with a stand-in function, then describe the samples
+  pwl::BuildParams bp;
+  pwl_status st = resolve_build(PWL_F_POLY, nullptr, 0, a, b, N, partition, values, &bp);
+  if (st != PWL_OK) return st;
+  bp.f.func = PWL_F_SAMPLED;
+  bp.f.sf = f;
+  bp.f.sf2 = f2;
+  bp.f.S = S;
+  bp.f.s_a = a;
+  bp.f.s_h = (b - a) / (double)S;
+  return create_table(bp, stream, out);
 }
 
 pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t nparams, double a,

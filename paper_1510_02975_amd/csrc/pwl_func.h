@@ -1,7 +1,8 @@
 // Device library of the approximated functions: FP32 values (vertex values
 // and the hat-function quadrature) and FP64 second derivatives (the knot
 // density of Sec. III-B1).  Gaussian (Sec. VI-A), Lorentzian (Sec. VI-B),
-// Bessel J0 (Sec. VI-C), plus two test functions with closed-form knots.
+// Bessel J0 (Sec. VI-C), two test functions with closed-form knots, and any
+// f given by samples of f and f'' (the method applies to any continuous f).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +10,32 @@
 #include "pwl_internal.h"
 
 namespace pwl {
+
+// A sampled f: the cubic spline with values f_i and second derivatives f''_i
+// at t_i.  On [t_i, t_{i+1}], u = (x - t_i) / h:
+//   f(x)   = (1-u) f_i + u f_{i+1} - h^2 u (1-u) ((2-u) f''_i + (1+u) f''_{i+1}) / 6,
+//   f''(x) = (1-u) f''_i + u f''_{i+1};
+// outside [t_0, t_S] the end intervals extend.
+__device__ inline int sample_cell(const FuncDesc& f, double x, double* u) {
+  const double s = (x - f.s_a) / f.s_h;
+  double c = floor(s);
+  c = fmin(fmax(c, 0.0), (double)(f.S - 1));
+  *u = s - c;
+  return (int)c;
+}
+
+__device__ inline double sampled_value(const FuncDesc& f, double x) {
+  double u;
+  const int i = sample_cell(f, x, &u);
+  const double w = u * (1.0 - u) * f.s_h * f.s_h / 6.0;
+  return (1.0 - u) * f.sf[i] + u * f.sf[i + 1] - w * ((2.0 - u) * f.sf2[i] + (1.0 + u) * f.sf2[i + 1]);
+}
+
+__device__ inline double sampled_second(const FuncDesc& f, double x) {
+  double u;
+  const int i = sample_cell(f, x, &u);
+  return (1.0 - u) * f.sf2[i] + u * f.sf2[i + 1];
+}
 
 __device__ inline float f_value32(const FuncDesc& f, float x) {
   switch (f.func) {
@@ -29,6 +56,8 @@ __device__ inline float f_value32(const FuncDesc& f, float x) {
     }
     case PWL_F_EXP:
       return f.p32[1] * expf(f.p32[0] * x);
+    case PWL_F_SAMPLED:
+      return (float)sampled_value(f, (double)x);
     default:
       return __builtin_nanf("");
   }
@@ -63,6 +92,8 @@ __device__ inline double f_second64(const FuncDesc& f, double x) {
       const double al = f.p[0];
       return f.p[1] * al * al * exp(al * x);
     }
+    case PWL_F_SAMPLED:
+      return sampled_second(f, x);
     default:
       return __builtin_nan("");
   }

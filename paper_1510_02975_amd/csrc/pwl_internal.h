@@ -24,6 +24,11 @@ struct FuncDesc {
   int32_t nparams;
   double p[PWL_MAX_PARAMS];   // Gaussian {s, amp}; Lorentzian {g, amp}; J0 {amp}; poly c0..c5; exp {alpha, amp}
   float p32[PWL_MAX_PARAMS];  // the same, rounded to FP32 (FP32 evaluations)
+  // PWL_F_SAMPLED: f and f'' at t_i = s_a + i s_h, i = 0..S (device FP64)
+  const double* sf;
+  const double* sf2;
+  int32_t S;
+  double s_a, s_h;
 };
 
 // Device view of a table's persistent arrays.

@@ -176,3 +176,20 @@ def test_set_locate_validation():
     assert lib.pwl_get_locate() == 0
     assert lib.pwl_set_locate(1) == 0 and lib.pwl_get_locate() == 1
     assert lib.pwl_set_locate(0) == 0 and lib.pwl_get_locate() == 0
+
+
+def test_build_sampled_rejects_invalid_arguments_on_host():
+    lib = library()
+    out = ctypes.c_void_p(5)
+    f = ctypes.c_void_p(16)    # never dereferenced: validation fails first
+    assert lib.pwl_build_sampled(None, f, 8, 0.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
+    assert lib.pwl_build_sampled(f, None, 8, 0.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
+    assert lib.pwl_build_sampled(f, f, 0, 0.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
+    assert lib.pwl_build_sampled(f, f, 8, 1.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
+    assert lib.pwl_build_sampled(f, f, 8, 0.0, 1.0, 0, 1, 1, None, ctypes.byref(out)) == -1
+    assert lib.pwl_build_sampled(f, f, 8, 0.0, 1.0, 16, 9, 1, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert lib.pwl_build_sampled(f, f, 8, 0.0, 1.0, 16, 1, 1, None, None) == -1
+    # the sampled id is not a parameterised function
+    p = (ctypes.c_double * 1)(1.0)
+    assert lib.pwl_build(32, p, 1, 0.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
