@@ -16,7 +16,8 @@ Prints one JSON line.  Secondary figures ride along in "extra": the fused
 forward+backward on the gradient workload, direct expf, copy bandwidth, the
 Lorentzian and J0 tables at N = 256, 1024, 4096, and the many-table workload
 (one batched launch, its graph replay, the fused backward, and one launch per
-table).
+table), and the paper's sample application (per-pixel sums of Gaussian
+kernels through the table, expf and __expf).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 20]
 """
@@ -301,7 +302,8 @@ def batch_extra(torch, P, W, dev, args):
 def c3_extra(torch, P, W, dev):
     """Lorentzian on [-20, 20] and J0 on [0, 50], optimal partition, N in
     {256, 1024, 4096}, projection values, 2^27 uniform points: forward
-    throughput per table size (the LDS footprint grows with N)."""
+    throughput per table size (the LDS footprint grows with N), and the same
+    functions evaluated directly (no table)."""
     out = {}
     for spec in (W.LORENTZ, W.BESSEL):
         n = spec["n"]
@@ -316,7 +318,31 @@ def c3_extra(torch, P, W, dev):
             out[key + "_gpoints_s"] = n / s / 1e9
             out[key + "_hbm_frac"] = FWD_BYTES_PER_POINT * n / s / 1e9 / HBM_PEAK_GBS
             t.free()
+        # the same function evaluated directly with the device math library
+        s = timed_median(torch, lambda i: P.pwl_direct_eval(spec["func"], spec["params"], xs[i % 2], ys[i % 2]))
+        out["direct_%s_gpoints_s" % spec["name"].split("_")[0]] = n / s / 1e9
         del xs, ys
+    return out
+
+
+def kde_extra(torch, P, W, dev):
+    """The sample application (per-pixel sums of Gaussian kernels, T = 16
+    reference frames, 5 x 5 windows: 1200 kernel values per pixel) at CIF
+    and 1080p, with the kernel through a table of exp(-u^2/2) on [0, 8]
+    (optimal, N = 1024, projection), expf and __expf: mean time per pixel."""
+    c = W.KDE_CIF
+    t = P.pwl_build(0, (1.0, 1.0), 0.0, 8.0, 1024, 1, 1)
+    out = {}
+    for label, H, Wd in (("cif", c["H"], c["W"]), ("1080p", 1080, 1920)):
+        f_h, h_h = W.kde_frames(H, Wd, c["T"], seed=4)
+        f, h = torch.from_numpy(f_h).to(dev), torch.from_numpy(h_h).to(dev)
+        y = torch.empty((H, Wd), dtype=torch.float32, device=dev)
+        for name, mode in (("table", P.KDE_TABLE), ("expf", P.KDE_EXPF), ("fast_expf", P.KDE_FAST_EXPF)):
+            s = timed_median(torch, lambda i: P.pwl_kde(t, mode, f, h, c["radius"], c["sigma"], y), reps=10)
+            out["kde_%s_%s_ns_per_pixel" % (label, name)] = s / (H * Wd) * 1e9
+        del f, h, y
+    t.free()
+    out["kde_kernel_values_per_pixel"] = 3 * c["T"] * (2 * c["radius"] + 1) ** 2
     return out
 
 
@@ -495,6 +521,8 @@ def main():
         tg.free()
         log("extras: Lorentzian and J0 tables, 2^27 points")
         extra.update(c3_extra(torch, P, W, dev))
+        log("extras: sample application (per-pixel kernel sums)")
+        extra.update(kde_extra(torch, P, W, dev))
         if not args.no_batch:
             extra.update(batch_extra(torch, P, W, dev, args))
 

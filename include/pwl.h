@@ -311,8 +311,42 @@ void pwl_batch_free(pwl_batch* bt);
 pwl_status pwl_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int32_t fast,
                                void* stream);
 
+/*
+ * pwl_direct_eval - y = f(x) evaluated directly in FP32 with the device math
+ * library (expf, j0f, IEEE division; no table): the baseline each table is
+ * compared with (Sec. VI).  func and params as in pwl_build (not
+ * PWL_F_SAMPLED); x, y device FP32 [n].
+ */
+pwl_status pwl_direct_eval(int32_t func, const double* params, int32_t nparams, const float* x, float* y, int64_t n,
+                           void* stream);
+
 /* pwl_copy - dst = src (device FP32 [n]); the HBM bandwidth probe. */
 pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream);
+
+/* ---- sample application ------------------------------------------------- */
+
+#define PWL_KDE_TABLE 0       /* kernel values through the table                 */
+#define PWL_KDE_EXPF 1        /* expf                                             */
+#define PWL_KDE_FAST_EXPF 2   /* __expf                                           */
+
+/*
+ * pwl_kde - per-pixel sums of Gaussian kernels of a nonparametric background
+ * model, the application the paper accelerates with its tables (Sec. VI-A):
+ *   out[y, x] = 1 / (T (2r+1)^2) * sum over k < T and the (2r+1)^2 window of
+ *               (y, x) (clamped to the image) of
+ *               prod_{c = 0, 1, 2} g((frame[y, x, c] - hist[k, y', x', c]) / sigma[c]),
+ * g(u) = exp(-u^2 / 2).  frame is DEVICE RGBA8 [H, W, 4], hist DEVICE RGBA8
+ * [T, H, W, 4] (alpha ignored), sigma a HOST array of 3 positive values, out
+ * DEVICE FP32 [H, W].  mode PWL_KDE_TABLE evaluates g through `t` (a table
+ * of exp(-u^2/2); its argument is |u| when the table's domain starts at 0,
+ * so a table on [0, 8] serves, as in the paper); the other modes ignore `t`
+ * (may be NULL).  1 <= H, W; 1 <= T; 0 <= r <= 32.  Sums are accumulated in
+ * FP64; each kernel value is FP32.
+ */
+pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const void* hist, int32_t H, int32_t W,
+                   int32_t T, int32_t r, const float* sigma, float* out, void* stream);
+
+
 
 /* ---- launch tuning -------------------------------------------------------- */
 

@@ -560,3 +560,35 @@ def result1_bound(func, params, X, grid_per_segment=65):
     xs = X[:-1, None] + h[:, None] * s[None, :]
     m = np.abs(f_second(func, params, xs)).max(axis=1)
     return math.sqrt(float(np.sum(m * m * h ** 5 / 120.0)))
+
+
+# ---------------------------------------------------------------------------
+# Sample application (Sec. VI-A): per-pixel sums of Gaussian kernels of a
+# nonparametric background model.
+# ---------------------------------------------------------------------------
+
+def kde_likelihood(frame, hist, radius, sigma, g=None):
+    """For every pixel (y, x) of frame [H, W, >=3] the mean, over the T
+    reference frames hist [T, H, W, >=3] and the (2r+1) x (2r+1) window of
+    (y, x) (indices clamped to the image), of prod_c g((frame[y, x, c] -
+    hist[k, y', x', c]) / sigma[c]) over the first three channels, with
+    g(u) = exp(-u^2 / 2) unless another g is given."""
+    if g is None:
+        def g(u):
+            return np.exp(-0.5 * u * u)
+    f = np.asarray(frame)[..., :3].astype(np.float64)
+    h = np.asarray(hist)[..., :3].astype(np.float64)
+    T, H, W = h.shape[:3]
+    ys, xs = np.arange(H), np.arange(W)
+    acc = np.zeros((H, W))
+    for k in range(T):
+        for dy in range(-radius, radius + 1):
+            yy = np.clip(ys + dy, 0, H - 1)
+            for dx in range(-radius, radius + 1):
+                xx = np.clip(xs + dx, 0, W - 1)
+                hk = h[k][yy][:, xx]
+                term = np.ones((H, W))
+                for c in range(3):
+                    term = term * g((f[..., c] - hk[..., c]) / float(sigma[c]))
+                acc += term
+    return acc / (T * (2 * radius + 1) ** 2)

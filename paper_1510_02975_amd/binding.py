@@ -60,6 +60,8 @@ _SIGNATURES = {
     "pwl_locate": (_c_int32, [_vp, _vp, _vp, _c_int64, _vp]),
     "pwl_direct_gaussian": (_c_int32, [_vp, _vp, _c_int64, ctypes.c_float, ctypes.c_float, _c_int32, _vp]),
     "pwl_copy": (_c_int32, [_vp, _vp, _c_int64, _vp]),
+    "pwl_direct_eval": (_c_int32, [_c_int32, _dp, _c_int32, _vp, _vp, _c_int64, _vp]),
+    "pwl_kde": (_c_int32, [_vp, _c_int32, _vp, _vp, _c_int32, _c_int32, _c_int32, _c_int32, _fp, _vp, _vp]),
     "pwl_batch_create": (_c_int32, [ctypes.POINTER(_vp), _c_int32, ctypes.POINTER(_c_int64), _vp,
                                     ctypes.POINTER(_vp)]),
     "pwl_batch_eval": (_c_int32, [_vp, _vp, _vp, _vp]),
@@ -420,6 +422,36 @@ def pwl_get_launch(kernel):
 
 
 LOCATE_MAP, LOCATE_SEARCH = 0, 1
+KDE_TABLE, KDE_EXPF, KDE_FAST_EXPF = 0, 1, 2
+
+
+def pwl_direct_eval(func, params, x, y=None, stream=None):
+    """y = f(x) in FP32 with the device math library (no table)."""
+    if y is None:
+        y = torch.empty_like(x)
+    if y.numel() != x.numel():
+        raise ValueError("y must have as many elements as x")
+    arr, npar = _params(params)
+    _check(load_library().pwl_direct_eval(int(func), arr, npar, _ptr(x, name="x"), _ptr(y, name="y"), x.numel(),
+                                          _stream(stream)))
+    return y
+
+
+def pwl_kde(table, mode, frame, hist, radius, sigma, out=None, stream=None):
+    """Per-pixel sums of Gaussian kernels: frame uint8 [H, W, 4], hist uint8
+    [T, H, W, 4] (device); returns FP32 [H, W]."""
+    if frame.dtype != torch.uint8 or hist.dtype != torch.uint8:
+        raise TypeError("frame and hist must be uint8 RGBA")
+    if frame.dim() != 3 or frame.shape[2] != 4 or hist.dim() != 4 or tuple(hist.shape[1:]) != tuple(frame.shape):
+        raise ValueError("need frame [H, W, 4] and hist [T, H, W, 4]")
+    H, W = int(frame.shape[0]), int(frame.shape[1])
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=frame.device)
+    sig = (ctypes.c_float * 3)(*[float(s) for s in sigma])
+    _check(load_library().pwl_kde(table.handle if table is not None else None, int(mode),
+                                  _ptr(frame, torch.uint8, "frame"), _ptr(hist, torch.uint8, "hist"), H, W,
+                                  int(hist.shape[0]), int(radius), sig, _ptr(out, name="out"), _stream(stream)))
+    return out
 
 
 def pwl_set_locate(mode):

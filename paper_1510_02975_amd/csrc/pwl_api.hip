@@ -18,6 +18,7 @@
 
 namespace pwl {
 hipError_t configure_build_kernels(int max_lds);
+hipError_t configure_kde_kernels(int max_lds);
 hipError_t configure_eval_kernels(int max_lds);
 }  // namespace pwl
 
@@ -84,6 +85,7 @@ pwl_status device_ready(int* dev_out, int* num_cu, int* max_lds = nullptr) {
     if (e == hipSuccess) e = pwl::configure_build_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_eval_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_batch_kernels(lds);
+    if (e == hipSuccess) e = pwl::configure_kde_kernels(lds);
     g_num_cu[dev] = cu > 0 ? cu : 1;
     g_max_lds[dev] = lds;
     g_cfg_err[dev] = e;
@@ -533,6 +535,21 @@ pwl_status pwl_direct_gaussian(const float* x, float* y, int64_t n, float s, flo
   return PWL_OK;
 }
 
+pwl_status pwl_direct_eval(int32_t func, const double* params, int32_t nparams, const float* x, float* y, int64_t n,
+                           void* stream) {
+  pwl::FuncDesc f;
+  pwl_status st = resolve_func(func, params, nparams, &f);
+  if (st != PWL_OK) return st;
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (n == 0) return PWL_OK;
+  if (x == nullptr || y == nullptr) return fail(PWL_EINVAL, "x and y must be non-NULL");
+  int num_cu = 1;
+  st = device_ready(nullptr, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(pwl::launch_direct_func(f, x, y, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
 pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
   if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
   if (n == 0) return PWL_OK;
@@ -541,6 +558,26 @@ pwl_status pwl_copy(const float* src, float* dst, int64_t n, void* stream) {
   pwl_status st = device_ready(nullptr, &num_cu);
   if (st != PWL_OK) return st;
   PWL_HIP(pwl::launch_copy(src, dst, n, num_cu, static_cast<hipStream_t>(stream)));
+  return PWL_OK;
+}
+
+pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const void* hist, int32_t H, int32_t W,
+                   int32_t T, int32_t r, const float* sigma, float* out, void* stream) {
+  if (mode != PWL_KDE_TABLE && mode != PWL_KDE_EXPF && mode != PWL_KDE_FAST_EXPF)
+    return fail(PWL_EINVAL, "unknown kde mode %d", mode);
+  if (H < 1 || W < 1 || T < 1) return fail(PWL_EINVAL, "need H, W, T >= 1 (got %d, %d, %d)", H, W, T);
+  if (r < 0 || r > 32) return fail(PWL_EINVAL, "window radius must be in [0, 32], got %d", r);
+  if (frame == nullptr || hist == nullptr || out == nullptr || sigma == nullptr)
+    return fail(PWL_EINVAL, "frame, hist, sigma and out must be non-NULL");
+  for (int c = 0; c < 3; ++c)
+    if (!(sigma[c] > 0.0f) || !std::isfinite(sigma[c])) return fail(PWL_EINVAL, "sigma[%d] must be > 0", c);
+  if (mode == PWL_KDE_TABLE && t == nullptr) return fail(PWL_EINVAL, "the table mode needs a table");
+  int num_cu = 1;
+  pwl_status st = (mode == PWL_KDE_TABLE) ? check_table(t, &num_cu) : device_ready(nullptr, &num_cu);
+  if (st != PWL_OK) return st;
+  pwl::EvalTable e{};
+  if (mode == PWL_KDE_TABLE) e = eval_view(t);
+  PWL_HIP(pwl::launch_kde(e, mode, frame, hist, H, W, T, r, sigma, out, static_cast<hipStream_t>(stream)));
   return PWL_OK;
 }
 

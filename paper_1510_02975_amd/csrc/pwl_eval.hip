@@ -8,11 +8,14 @@
 // backward), so there is no matrix-core work: the only per-point work is the
 // map lookup, a short knot compare loop in LDS, one 16-byte record read and
 // one FMA.  The backward accumulates dL/dv in LDS with FP64 atomics and
-// flushes it once per workgroup with global FP32 atomics.
+// writes one column of per-workgroup partial sums, which k_dv_reduce adds.
+// Baselines: direct FP32 evaluation of f (the device math library), expf /
+// __expf Gaussians, and a copy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "pwl_func.h"
 #include "pwl_internal.h"
 #include "pwl_locate.h"
 #include "pwl_stream.h"
@@ -174,6 +177,37 @@ __global__ __launch_bounds__(256) void k_direct_gaussian(const float* __restrict
     }
   }
   PWL_SCALAR_TAIL(y[i] = amp * (kFast ? __expf(c * x[i] * x[i]) : expf(c * x[i] * x[i])))
+}
+
+// Direct FP32 evaluation of f at every point, the same streaming shape.
+__global__ __launch_bounds__(256) void k_direct_func(FuncDesc f, const float* __restrict__ x,
+                                                     float* __restrict__ y, int64_t n4, int64_t n) {
+  constexpr int kUnroll = kStreamUnroll;
+  const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x);
+  v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y);
+  const int64_t bs = blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * bs * kUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * bs * kUnroll + threadIdx.x; base < n4; base += stride) {
+    v4f xv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * bs;
+      if (i < n4) xv[u] = __builtin_nontemporal_load(x4 + i);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + u * bs;
+      if (i < n4) {
+        v4f yv;
+        yv.x = f_value32(f, xv[u].x);
+        yv.y = f_value32(f, xv[u].y);
+        yv.z = f_value32(f, xv[u].z);
+        yv.w = f_value32(f, xv[u].w);
+        __builtin_nontemporal_store(yv, y4 + i);
+      }
+    }
+  }
+  PWL_SCALAR_TAIL(y[i] = f_value32(f, x[i]))
 }
 
 __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, float* __restrict__ dst,
@@ -364,6 +398,13 @@ hipError_t launch_direct_gaussian(const float* x, float* y, int64_t n, float sg,
     hipLaunchKernelGGL(k_direct_gaussian<true>, dim3(ls.grid), dim3(ls.block), 0, s, x, y, n4, n, c, amp);
   else
     hipLaunchKernelGGL(k_direct_gaussian<false>, dim3(ls.grid), dim3(ls.block), 0, s, x, y, n4, n, c, amp);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_func(const FuncDesc& f, const float* x, float* y, int64_t n, int num_cu, hipStream_t s) {
+  const int64_t n4 = (aligned16(x) && aligned16(y)) ? n / 4 : 0;
+  const LaunchShape ls = baseline_shape(n4, n, num_cu);
+  hipLaunchKernelGGL(k_direct_func, dim3(ls.grid), dim3(ls.block), 0, s, f, x, y, n4, n);
   return hipGetLastError();
 }
 

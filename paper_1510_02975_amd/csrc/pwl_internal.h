@@ -182,6 +182,10 @@ hipError_t launch_locate(const EvalTable& t, const float* x, int32_t* seg, int64
 hipError_t launch_direct_gaussian(const float* x, float* y, int64_t n, float s, float amp, int fast,
                                   int num_cu, hipStream_t st);
 hipError_t launch_copy(const float* src, float* dst, int64_t n, int num_cu, hipStream_t s);
+hipError_t launch_direct_func(const FuncDesc& f, const float* x, float* y, int64_t n, int num_cu, hipStream_t s);
+hipError_t launch_kde(const EvalTable& t, int mode, const void* frame, const void* hist, int H, int W, int T,
+                      int r, const float* sigma, float* out, hipStream_t s);
+hipError_t configure_kde_kernels(int max_lds);
 hipError_t configure_kernels();   // raise dynamic-LDS limits once per process
 
 }  // namespace pwl

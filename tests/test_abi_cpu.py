@@ -193,3 +193,17 @@ def test_build_sampled_rejects_invalid_arguments_on_host():
     # the sampled id is not a parameterised function
     p = (ctypes.c_double * 1)(1.0)
     assert lib.pwl_build(32, p, 1, 0.0, 1.0, 16, 1, 1, None, ctypes.byref(out)) == -1
+
+
+def test_kde_rejects_invalid_arguments_on_host():
+    lib = library()
+    buf = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    s = (ctypes.c_float * 3)(6.0, 6.0, 6.0)
+    bad_s = (ctypes.c_float * 3)(6.0, 0.0, 6.0)
+    assert lib.pwl_kde(None, 3, buf, buf, 8, 8, 2, 1, s, buf, None) == -1      # mode
+    assert lib.pwl_kde(None, 1, buf, buf, 0, 8, 2, 1, s, buf, None) == -1      # H
+    assert lib.pwl_kde(None, 1, buf, buf, 8, 8, 0, 1, s, buf, None) == -1      # T
+    assert lib.pwl_kde(None, 1, buf, buf, 8, 8, 2, 33, s, buf, None) == -1     # radius
+    assert lib.pwl_kde(None, 1, buf, buf, 8, 8, 2, 1, bad_s, buf, None) == -1  # sigma
+    assert lib.pwl_kde(None, 1, None, buf, 8, 8, 2, 1, s, buf, None) == -1     # frame
+    assert lib.pwl_kde(None, 0, buf, buf, 8, 8, 2, 1, s, buf, None) == -1      # table mode, no table

@@ -130,3 +130,39 @@ def many_tables_points(tables, seed=0):
         m = t["n"]
         x[offs[i]:offs[i + 1]] = (t["a"] + (t["b"] - t["a"]) * rng.random(m)).astype(np.float32)
     return x, offs
+
+
+# --- sample application: per-pixel sums of Gaussian kernels ----------------
+# Nonparametric background model (Sec. VI-A): every pixel of the current
+# frame is compared with the pixels of a (2r+1) x (2r+1) window in each of T
+# reference frames.  Synthetic scene: a smooth colour field that drifts and
+# flickers from frame to frame, plus sensor noise, and a moving square
+# "foreground" object in the current frame.  RGBA8, alpha 255.
+KDE_CIF = dict(name="kde_cif", H=288, W=352, T=16, radius=2, sigma=(6.0, 6.0, 6.0))
+
+
+def kde_frames(H, W, T, seed=3):
+    """(frame [H, W, 4] uint8, history [T, H, W, 4] uint8)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    phase = rng.uniform(0.0, 2.0 * math.pi, 3)
+
+    def scene(shift, gain):
+        out = np.empty((H, W, 4), dtype=np.float64)
+        for c in range(3):
+            out[..., c] = 128.0 + 60.0 * np.sin(0.02 * (xx + shift) + 0.03 * yy + phase[c]) * gain
+        out[..., 3] = 255.0
+        return out
+
+    hist = np.empty((T, H, W, 4), dtype=np.uint8)
+    for t in range(T):
+        f = scene(0.7 * t, 1.0 + 0.02 * rng.standard_normal())
+        f[..., :3] += 4.0 * rng.standard_normal((H, W, 3))
+        hist[t] = np.clip(np.rint(f), 0, 255).astype(np.uint8)
+    cur = scene(0.7 * T, 1.0)
+    cur[..., :3] += 4.0 * rng.standard_normal((H, W, 3))
+    s = max(4, min(H, W) // 6)
+    y0, x0 = H // 3, W // 2
+    cur[y0:y0 + s, x0:x0 + s, :3] = rng.uniform(0.0, 255.0, 3)   # the foreground square
+    frame = np.clip(np.rint(cur), 0, 255).astype(np.uint8)
+    return frame, hist
