@@ -50,11 +50,11 @@ __device__ __forceinline__ void batch_fwd_run(const BatchRun& r, const Smem& s, 
   const EvalTable t = run_table(r);
   switch (r.maxc) {
     case 0:
-    case 1: fwd_range<U, 1>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
-    case 2: fwd_range<U, 2>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
-    case 3: fwd_range<U, 3>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
-    case 4: fwd_range<U, 4>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
-    default: fwd_range<U, 0>(t, s, x, y, r.begin, r.end, vec, 0, 1); break;
+    case 1: fwd_run<U, 1>(t, s, x, y, r.begin, r.end, vec); break;
+    case 2: fwd_run<U, 2>(t, s, x, y, r.begin, r.end, vec); break;
+    case 3: fwd_run<U, 3>(t, s, x, y, r.begin, r.end, vec); break;
+    case 4: fwd_run<U, 4>(t, s, x, y, r.begin, r.end, vec); break;
+    default: fwd_run<U, 0>(t, s, x, y, r.begin, r.end, vec); break;
   }
 }
 

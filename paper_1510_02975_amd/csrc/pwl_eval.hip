@@ -250,10 +250,11 @@ inline bool same_phase(const void* a, const void* b) {
 // fused backward at 2^26 points, two vectors per thread (the dL/dv LDS
 // atomics favour a smaller register footprint) in one 768-thread workgroup
 // per CU.  Register use, not the grid, caps residency: the grid size sets
-// how finely the points are dealt out.  The batched kernels stage a table per run and run
-// best with one 1024-thread workgroup per CU, one vector per thread (every
-// table then shares one launch).  pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 768, 1}, {1, 1024, 1}, {1, 1024, 1}};
+// how finely the points are dealt out.  The batched kernels stage a table
+// per run and run best with one 1024-thread workgroup per CU (every table
+// then shares one launch), two vectors per thread forward and one in the
+// fused backward.  pwl_set_launch overrides them.
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 768, 1}, {2, 1024, 1}, {1, 1024, 1}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 
