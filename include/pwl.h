@@ -358,10 +358,15 @@ pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const vo
 /*
  * pwl_set_launch - process-wide launch shape of one evaluation kernel family:
  * each thread streams `unroll` (1, 2 or 4) 16-byte vectors per iteration,
- * workgroups have `block` threads (a multiple of 64 in [64, 1024]) and
- * `wg_per_cu` of them are launched per compute unit (fewer when the table's
- * LDS footprint does not allow that many).  All three zero restores the
- * default.  Used by the autotuner; takes effect for later launches.
+ * workgroups have `block` threads (a multiple of 64 in [64, 1024]) and the
+ * grid holds up to `wg_per_cu` (1..32) of them per compute unit, more than
+ * can be resident at once if asked (later ones start as earlier ones end).
+ * The single-table kernels cut the grid back, a whole workgroup per compute
+ * unit at a time and to no fewer than one per compute unit, until each
+ * workgroup streams at least 2^16 points and 2 points per byte of the table
+ * it stages in LDS.  All three
+ * zero restores the default.  Used by the autotuner; takes effect for later
+ * launches.
  * pwl_get_launch reads the current shape back (outputs nullable).
  */
 pwl_status pwl_set_launch(int32_t kernel, int32_t unroll, int32_t block, int32_t wg_per_cu);

@@ -21,7 +21,7 @@ from . import binding as B
 DEFAULT_CANDIDATES = {
     "unroll": (1, 2, 4),
     "block": (256, 512, 768, 1024),
-    "wg_per_cu": (1, 2, 3, 4),
+    "wg_per_cu": (1, 2, 4, 8, 16, 24),
 }
 
 
@@ -44,8 +44,6 @@ def tune(kernel, run, candidates=None, reps=10, verbose=False):
     cand.update(candidates or {})
     results = []
     for u, blk, w in itertools.product(cand["unroll"], cand["block"], cand["wg_per_cu"]):
-        if blk * w > 2048:
-            continue
         B.pwl_set_launch(kernel, u, blk, w)
         t = _time(run, reps)
         results.append((t, (u, blk, w)))
@@ -72,8 +70,6 @@ def tune_batch(tables, offsets, x, y, g=None, dx=None, dv=None, candidates=None,
     for kernel, make in kinds:
         results = []
         for u, blk, w in itertools.product(cand["unroll"], cand["block"], cand["wg_per_cu"]):
-            if blk * w > 2048:
-                continue
             B.pwl_set_launch(kernel, u, blk, w)
             bt = B.pwl_batch_create(tables, offsets)
             t = _time(make(bt), reps)

@@ -27,6 +27,8 @@ namespace {
 constexpr int kStreamUnroll = 4;    // float4 vectors per thread per iteration (baselines)
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kXcds = 8;             // MI355X accelerator complex dies; workgroups go to them round-robin
+constexpr int64_t kMinPointsPerWG = int64_t(1) << 16;   // streaming grids: points per workgroup, at least
+constexpr int64_t kPointsPerStagedByte = 2;             // and per byte of table the workgroup stages
 
 using namespace stream;
 
@@ -241,31 +243,40 @@ inline bool same_phase(const void* a, const void* b) {
   return b == nullptr || ((reinterpret_cast<uintptr_t>(a) ^ reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
 }
 
-// Launch shape of a streaming evaluation kernel: `wg_per_cu` workgroups of
-// `block` threads per CU (fewer if the table's LDS does not allow that
-// many), each thread handling `unroll` float4 vectors per iteration, and
-// never more workgroups than there are vectors.  The defaults are the
-// autotuner's choice on MI355X: forward at 2^28 points, four vectors per
-// thread in 1024-thread workgroups, a grid of two workgroups per CU;
-// fused backward at 2^26 points, two vectors per thread (the dL/dv LDS
-// atomics favour a smaller register footprint) in one 768-thread workgroup
-// per CU.  Register use, not the grid, caps residency: the grid size sets
-// how finely the points are dealt out.  The batched kernels stage a table
-// per run and run best with one 1024-thread workgroup per CU (every table
-// then shares one launch), two vectors per thread forward and one in the
-// fused backward.  pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 2}, {2, 768, 1}, {2, 1024, 1}, {1, 1024, 1}};
+// Launch shape of a streaming evaluation kernel: workgroups of `block`
+// threads, each thread handling `unroll` float4 vectors per iteration, on a
+// grid of up to `wg_per_cu` workgroups per CU.  The grid may be many times
+// what the CUs hold at once (register use caps residency at one 1024-thread
+// workgroup per CU): workgroups are then dispatched as CUs free up, so CUs
+// and XCDs that stream faster take more of the points, where a grid of one
+// resident round waits for its slowest CU.  Each workgroup stages the whole
+// table, so the grid is cut back, a whole workgroup per CU at a time (a
+// partial last round leaves CUs idle), until a workgroup streams at least
+// kMinPointsPerWG points and at least kPointsPerStagedByte points per byte
+// of table it stages, but never below one workgroup per CU (nor above one
+// per iteration of work).  The defaults are the autotuner's choice on
+// MI355X: forward at 2^28 points, four vectors per thread in 1024-thread
+// workgroups, up to 16 per CU (12 to 24 measure alike at N = 1024; at
+// N = 4096 the staging rule leaves about 3); fused backward at 2^26 points,
+// two vectors per thread (the dL/dv LDS atomics favour a smaller register
+// footprint) in one 768-thread workgroup per CU - every further workgroup
+// there adds a dL/dv flush and a column to reduce, and larger grids measure
+// slower.  The batched kernels stage a table per run and run best with one
+// 1024-thread workgroup per CU (every table then shares one launch), two
+// vectors per thread forward and one in the fused backward.
+// pwl_set_launch overrides them.
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 1}, {1, 1024, 1}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 
 LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t n, int num_cu) {
-  const int wg_lds = (int)std::max<size_t>(1, kLdsPerCU / std::max<size_t>(lds, 1));
-  const int wg_per_cu = std::max(1, std::min(c.wg_per_cu, wg_lds));
   const int block = c.block;
   const int64_t per_wg = (int64_t)block * c.unroll;
   const int64_t work = (n4 > 0) ? (n4 + per_wg - 1) / per_wg : (n + block - 1) / block;
-  int64_t grid = (int64_t)num_cu * wg_per_cu;
-  grid = std::max<int64_t>(1, std::min<int64_t>(grid, work));
+  const int64_t min_points = std::max<int64_t>(kMinPointsPerWG, kPointsPerStagedByte * (int64_t)lds);
+  // whole workgroups per CU: a last partial round would leave CUs idle
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(c.wg_per_cu, n / (min_points * num_cu)));
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cu * per_cu, work));
   return LaunchShape{block, (int)grid, lds};
 }
 
