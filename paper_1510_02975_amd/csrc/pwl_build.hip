@@ -10,7 +10,7 @@
 //                        projection (Sec. II-B2) FP32 Gauss-Legendre integrals of f
 //                        against the hats and the FP64 solve of M c = b (parallel
 //                        cyclic reduction), and the packed records
-//                        {x_k, v_k, slope_k, 1/h_k}
+//                        {x_k, v_k, slope_k, x_{k+1}}
 #include <hip/hip_runtime.h>
 
 #include "pwl_func.h"
@@ -204,7 +204,7 @@ constexpr int kRowsPerThread = (PWL_MAX_N + 1 + kFinalizeThreads - 1) / kFinaliz
 //  3. (projection) <f, phi_k> by 16-point Gauss-Legendre per segment, one
 //     thread per segment;
 //  4. (projection) the FP64 solve of M c = b by parallel cyclic reduction;
-//  5. the packed records {x_k, v_k, slope_k, 1/h_k} (NaN for a collapsed
+//  5. the packed records {x_k, v_k, slope_k, x_{k+1}} (NaN for a collapsed
 //     table, whose map is then cleared).
 __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, TableDev td) {
   extern __shared__ double s_pcr[];
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(BuildParams bp, T
     r.x = x0;
     r.y = (float)D[k];
     r.z = (float)((v1 - v0) / h);
-    r.w = (float)(1.0 / h);
+    r.w = x1;
     if (collapsed) {
       r.y = __builtin_nanf("");
       r.z = __builtin_nanf("");

@@ -1,7 +1,7 @@
 // Streaming evaluation kernels (Algorithm 1, Sec. IV) for gfx950.
 //
 // Every workgroup stages the whole table in LDS once - packed records
-// {x_k, v_k, slope_k, 1/h_k}, the interior knots (NaN padded) and the
+// {x_k, v_k, slope_k, x_{k+1}}, the interior knots (NaN padded) and the
 // uniform index map - and then streams its share of the points with 16-byte
 // non-temporal loads and stores, U vectors per thread in flight.  The path is
 // a memory-bound gather (8 bytes per point forward, 16 fused forward and

@@ -33,7 +33,7 @@ struct FuncDesc {
 
 // Device view of a table's persistent arrays.
 struct TableDev {
-  float4* rec;        // [N]   {x_k, v_k, slope_k, 1/h_k}
+  float4* rec;        // [N]   {x_k, v_k, slope_k, x_{k+1}}
   float* knots;       // [N+1] FP32 knots
   uint16_t* lo;       // [K+1] uniform index map: lo[u] = #{interior knots in cells < u}
   float* values;      // [N+1] FP32 vertex values

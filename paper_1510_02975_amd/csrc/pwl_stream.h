@@ -15,7 +15,7 @@ namespace stream {
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct Smem {
-  float4* rec;      // [N]           {x_k, v_k, slope_k, 1/h_k}
+  float4* rec;      // [N]           {x_k, v_k, slope_k, x_{k+1}}
   float* knot;      // [N + pad]     knot[k] = x_k for 1 <= k <= N-1, NaN elsewhere
   uint16_t* lo;     // [K + 1]       lo[u] = #{interior knots in cells < u}; lo[K] = N - 1
   double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
@@ -26,14 +26,21 @@ __device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
   s.rec = reinterpret_cast<float4*>(base);
   s.knot = reinterpret_cast<float*>(s.rec + N);
   s.lo = reinterpret_cast<uint16_t*>(s.knot + N + kKnotPad);
-  s.dv = backward ? reinterpret_cast<double*>(
-                        (reinterpret_cast<uintptr_t>(s.lo + ((K + 2) & ~1)) + 15) & ~(uintptr_t)15)
-                  : nullptr;
+  if (backward) {
+    // 16-byte aligned by an offset from the LDS pointer itself: a pointer
+    // rebuilt from an integer would lose its address space, and the dL/dv
+    // atomics would go through the flat path instead of the LDS one
+    char* p = reinterpret_cast<char*>(s.lo + ((K + 2) & ~1));
+    s.dv = reinterpret_cast<double*>(p + ((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15));
+  } else {
+    s.dv = nullptr;
+  }
   return s;
 }
 
 // Copy the table into LDS.  With v_override the vertex values come from the
-// caller and slopes are re-derived as (v_{k+1} - v_k) / h_k in FP32.  The
+// caller and slopes are re-derived as (v_{k+1} - v_k) / (x_{k+1} - x_k) in
+// FP32.  The
 // knot sentinels are NaN so that every compare against them is false, even
 // for x = +inf.
 __device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo,
@@ -44,7 +51,7 @@ __device__ __forceinline__ void stage_table(const EvalTable& t, const float* __r
     if (vo != nullptr) {
       const float v0 = vo[k], v1 = vo[k + 1];
       r.y = v0;
-      r.z = (v1 - v0) * r.w;
+      r.z = (v1 - v0) / (r.w - r.x);
     }
     s.rec[k] = r;
   }
@@ -128,13 +135,13 @@ __device__ __forceinline__ void backward_point(float x, float g, const EvalTable
       // at full rate on gfx950 (FP32 ones take a slow path) and keep the
       // per-workgroup sums exact to FP32 output precision.  Workgroup scope,
       // relaxed: no point has to wait for the thread's outstanding stores.
-      // Each hat weight comes from its own knot distance, (x_{i+1} - x)/h and
-      // (x - x_i)/h: forming (1 - delta) g as g - delta g would cancel when
-      // delta is near 1.
+      // Each hat weight comes from its own knot distance, (x_{k+1} - x)/h and
+      // (x - x_k)/h, with x_{k+1} from the record: forming (1 - delta) g as
+      // g - delta g would cancel when delta is near 1.
       const float xc = clamp_nan(x, t.a32, t.b32);
-      const float x1 = (seg + 1 < t.N) ? s.knot[seg + 1] : t.b32;
-      const float w0 = ((x1 - xc) * r.w) * g;   // (1 - delta) g
-      const float w1 = (d * r.w) * g;           // delta g
+      const float rh = __builtin_amdgcn_rcpf(r.w - r.x);   // 1/h, within 1 ulp
+      const float w0 = ((r.w - xc) * rh) * g;   // (1 - delta) g
+      const float w1 = (d * rh) * g;            // delta g
       __hip_atomic_fetch_add(s.dv + seg, (double)w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __hip_atomic_fetch_add(s.dv + seg + 1, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
