@@ -591,7 +591,7 @@ namespace {
 constexpr int64_t kStagePoints = 4096;
 
 // Runs of one launch over the tables listed in `cls` (increasing table
-// order).  The class's work, taken in that order, is cut into `grid` chunks
+// order).  Their work, taken in that order, is cut into `grid` chunks
 // of equal cost, where a table with points costs kStagePoints (its staging)
 // plus its points, so a workgroup that meets many small tables gets fewer
 // points.  A chunk boundary inside a table is rounded down to a multiple of
@@ -609,7 +609,7 @@ void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, st
   }
   const int64_t total = voff[C];
   if (total == 0) return;
-  // boundary w: class table bj[w] at absolute point bp[w]; bj[grid] = C is the end
+  // boundary w: listed table bj[w] at absolute point bp[w]; bj[grid] = C is the end
   std::vector<int> bj(grid + 1, C);
   std::vector<int64_t> bp(grid + 1, 0);
   int j = 0;
@@ -646,35 +646,23 @@ struct ClassPlan {
   size_t lds = 0;
 };
 
-// Splits the tables by LDS footprint: those that fit `want` workgroups per CU
-// and the larger ones, each class with its own grid.  A class without points
-// gets no launch unless no class has points (then one empty launch remains,
-// so a call always launches something).
-std::vector<ClassPlan> plan_classes(const pwl_table* const* tables, int T, const int64_t* offsets, bool backward,
-                                    int num_cu, int max_lds, int want) {
-  const size_t lim = (size_t)max_lds / (size_t)std::max(1, want);
-  std::vector<int> cls[2];
-  size_t lds[2] = {0, 0};
-  int64_t pts[2] = {0, 0};
+// One launch per direction: a grid of `want` workgroups per CU over all the
+// tables, each workgroup reserving the LDS of the largest one.  Register use
+// keeps one 1024-thread workgroup resident per CU, so a grid of many per CU
+// runs as many short rounds, dispatched as CUs free up: CUs that stream
+// faster take more of the chunks, where a one-round grid waits for its
+// slowest CU.
+ClassPlan plan_batch(const pwl_table* const* tables, int T, const int64_t* offsets, bool backward, int num_cu,
+                     int want) {
+  ClassPlan p;
+  std::vector<int> all(T);
   for (int i = 0; i < T; ++i) {
-    const size_t l = pwl::batch_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward);
-    const int c = (l <= lim) ? 0 : 1;
-    cls[c].push_back(i);
-    lds[c] = std::max(lds[c], l);
-    pts[c] += offsets[i + 1] - offsets[i];
+    all[i] = i;
+    p.lds = std::max(p.lds, pwl::batch_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward));
   }
-  std::vector<ClassPlan> out;
-  for (int c = 0; c < 2; ++c) {
-    if (cls[c].empty()) continue;
-    if (pts[c] == 0 && (pts[0] + pts[1] > 0 || !out.empty())) continue;
-    ClassPlan p;
-    p.lds = lds[c];
-    const int by_lds = (int)std::max<size_t>(1, (size_t)max_lds / std::max<size_t>(p.lds, 1));
-    p.grid = num_cu * std::max(1, std::min(want, by_lds));
-    plan_runs(offsets, cls[c], p.grid, &p.runs, &p.begin);
-    out.push_back(std::move(p));
-  }
-  return out;
+  p.grid = num_cu * std::max(1, want);
+  plan_runs(offsets, all, p.grid, &p.runs, &p.begin);
+  return p;
 }
 
 }  // namespace
@@ -690,18 +678,18 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
     if (tables[i] == nullptr) return fail(PWL_EINVAL, "tables[%d] is NULL", i);
     if (offsets[i + 1] < offsets[i]) return fail(PWL_EINVAL, "offsets must be non-decreasing (at %d)", i);
   }
-  int dev = 0, num_cu = 1, max_lds = 0;
-  pwl_status st = device_ready(&dev, &num_cu, &max_lds);
+  int dev = 0, num_cu = 1;
+  pwl_status st = device_ready(&dev, &num_cu);
   if (st != PWL_OK) return st;
   for (int i = 0; i < T; ++i)
     if (tables[i]->device != dev)
       return fail(PWL_EINVAL, "tables[%d] lives on device %d, current is %d", i, tables[i]->device, dev);
   const int want_f = pwl::get_launch(PWL_KERNEL_BATCH).wg_per_cu;
   const int want_b = pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD).wg_per_cu;
-  std::vector<ClassPlan> plans[2] = {plan_classes(tables, T, offsets, false, num_cu, max_lds, want_f),
-                                     plan_classes(tables, T, offsets, true, num_cu, max_lds, want_b)};
+  ClassPlan plans[2] = {plan_batch(tables, T, offsets, false, num_cu, want_f),
+                        plan_batch(tables, T, offsets, true, num_cu, want_b)};
   // one allocation: tables, their deepest map cells, their images, then the
-  // runs and starts of every forward and backward launch
+  // runs and starts of the forward and the backward launch
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
@@ -712,12 +700,11 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
     nvec[i] = (int32_t)((pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, false) + 15) / 16);
     o_img[i] = take(16 * (size_t)nvec[i]);
   }
-  std::vector<size_t> o_runs, o_beg;
-  for (int dir = 0; dir < 2; ++dir)
-    for (const ClassPlan& p : plans[dir]) {
-      o_runs.push_back(take(sizeof(pwl::BatchRun) * std::max<size_t>(1, p.runs.size())));
-      o_beg.push_back(take(sizeof(int32_t) * p.begin.size()));
-    }
+  size_t o_runs[2], o_beg[2];
+  for (int dir = 0; dir < 2; ++dir) {
+    o_runs[dir] = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, plans[dir].runs.size()));
+    o_beg[dir] = take(sizeof(int32_t) * plans[dir].begin.size());
+  }
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, off);
   if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
@@ -743,12 +730,9 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   // complete the run descriptors and upload the plans
   pwl_batch* bt = new pwl_batch{};
-  bt->bl.nfwd = (int32_t)plans[0].size();
-  bt->bl.nbwd = (int32_t)plans[1].size();
-  size_t k = 0;
   for (int dir = 0; dir < 2; ++dir) {
-    for (size_t i = 0; i < plans[dir].size(); ++i, ++k) {
-      ClassPlan& p = plans[dir][i];
+    {
+      ClassPlan& p = plans[dir];
       for (pwl::BatchRun& r : p.runs) {
         const pwl_table* t = tables[r.table];
         r.img = hb[r.table].img;
@@ -762,13 +746,14 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
         r.maxc = maxc[r.table];
       }
       if (e == hipSuccess && !p.runs.empty())
-        e = hipMemcpyAsync(b + o_runs[k], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
+        e = hipMemcpyAsync(b + o_runs[dir], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
                            hipMemcpyHostToDevice, s);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(b + o_beg[k], p.begin.data(), sizeof(int32_t) * p.begin.size(), hipMemcpyHostToDevice, s);
-      pwl::BatchPlan& d = dir ? bt->bl.bwd[i] : bt->bl.fwd[i];
-      d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[k]), reinterpret_cast<int32_t*>(b + o_beg[k]),
-                         p.grid, (int32_t)p.runs.size(), p.lds};
+        e = hipMemcpyAsync(b + o_beg[dir], p.begin.data(), sizeof(int32_t) * p.begin.size(), hipMemcpyHostToDevice,
+                           s);
+      pwl::BatchPlan& d = dir ? bt->bl.bwd : bt->bl.fwd;
+      d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[dir]),
+                         reinterpret_cast<int32_t*>(b + o_beg[dir]), p.grid, (int32_t)p.runs.size(), p.lds};
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -879,19 +864,10 @@ pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int
   if (T) *T = bt->T;
   if (npoints) *npoints = bt->npoints;
   if (dv_len) *dv_len = bt->bl.dv_len;
-  int32_t gf = 0, gb = 0, rf = 0, rb = 0;
-  for (int k = 0; k < bt->bl.nfwd; ++k) {
-    gf += bt->bl.fwd[k].grid;
-    rf += bt->bl.fwd[k].nruns;
-  }
-  for (int k = 0; k < bt->bl.nbwd; ++k) {
-    gb += bt->bl.bwd[k].grid;
-    rb += bt->bl.bwd[k].nruns;
-  }
-  if (grid_fwd) *grid_fwd = gf;
-  if (grid_bwd) *grid_bwd = gb;
-  if (runs_fwd) *runs_fwd = rf;
-  if (runs_bwd) *runs_bwd = rb;
+  if (grid_fwd) *grid_fwd = bt->bl.fwd.grid;
+  if (grid_bwd) *grid_bwd = bt->bl.bwd.grid;
+  if (runs_fwd) *runs_fwd = bt->bl.fwd.nruns;
+  if (runs_bwd) *runs_bwd = bt->bl.bwd.nruns;
   return PWL_OK;
 }
 

@@ -1,17 +1,16 @@
 // Batched evaluation of many tables of uneven size over uneven point counts
-// in one persistent launch per table class.
+// in one launch.
 //
 // The points of all tables are concatenated (table t owns [off_t, off_{t+1})).
-// Tables are split into at most two classes by LDS footprint (those that fit
-// the configured workgroups per CU, and the larger ones).  Per class, the
-// host cuts the class's points into one contiguous, equally sized chunk per
-// workgroup and lists, per workgroup, the (table, begin, end) runs its chunk
-// covers.  A workgroup walks its runs in order, re-staging the LDS
-// table only when the table changes, and streams each run with the same
-// vectorised body as the single-table evaluator.  The fused backward keeps a
-// workgroup's dL/dv of the current table in FP64 LDS and flushes it with
-// global FP32 atomics into the concatenated gradient (table t at dv_off_t)
-// whenever the table changes and at the end.
+// The host cuts them into one contiguous chunk of equal cost per workgroup
+// (the grid holds many workgroups per CU, dispatched as CUs free up) and
+// lists, per workgroup, the (table, begin, end) runs its chunk covers.  A
+// workgroup walks its runs in order, re-staging the LDS table only when the
+// table changes, and streams each run with the same vectorised body as the
+// single-table evaluator.  The fused backward keeps a workgroup's dL/dv of
+// the current table in FP64 LDS and flushes it with global FP32 atomics into
+// the concatenated gradient (table t at dv_off_t) whenever the table changes
+// and at the end.
 #include <hip/hip_runtime.h>
 
 #include "pwl_internal.h"
@@ -232,11 +231,8 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
     const int64_t zgrid = std::min<int64_t>(1024, (bl.dv_len + 255) / 256);
     hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::max<int64_t>(1, zgrid)), dim3(256), 0, s, dv, bl.dv_len);
   }
-  const int np = backward ? bl.nbwd : bl.nfwd;
-  for (int k = 0; k < np; ++k) {
-    const hipError_t e = launch_plan(bl, backward ? bl.bwd[k] : bl.fwd[k], c, x, g, y, dx, dv, v, s);
-    if (e != hipSuccess) return e;
-  }
+  const hipError_t e = launch_plan(bl, backward ? bl.bwd : bl.fwd, c, x, g, y, dx, dv, v, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -261,11 +261,11 @@ inline bool same_phase(const void* a, const void* b) {
 // two vectors per thread (the dL/dv LDS atomics favour a smaller register
 // footprint) in one 768-thread workgroup per CU - every further workgroup
 // there adds a dL/dv flush and a column to reduce, and larger grids measure
-// slower.  The batched kernels stage a table per run and run best with one
-// 1024-thread workgroup per CU (every table then shares one launch), two
-// vectors per thread forward and one in the fused backward.
+// slower.  The batched kernels stage a table per run; they take 1024-thread
+// workgroups, 16 per CU, two vectors per thread forward and one in the fused
+// backward.
 // pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 1}, {1, 1024, 1}};
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 16}, {1, 1024, 16}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 

@@ -144,14 +144,9 @@ inline size_t batch_lds_bytes(int N, int K, bool backward) {
   return sizeof(BatchRun) * kRunSlots + ((eval_lds_bytes(N, K, backward) + 15) & ~(size_t)15);
 }
 
-// Tables whose LDS footprint allows the configured workgroups per CU form one
-// class; the larger tables form a second class with fewer, bigger
-// workgroups.  Each class is one persistent launch.
-constexpr int kMaxBatchClasses = 2;
-
+// One launch per direction over all the tables.
 struct BatchLaunch {
-  BatchPlan fwd[kMaxBatchClasses], bwd[kMaxBatchClasses];
-  int32_t nfwd, nbwd;        // launches per call
+  BatchPlan fwd, bwd;
   int64_t dv_len;            // sum over tables of N + 1
 };
 

@@ -1,4 +1,4 @@
-"""Batched multi-table evaluation (one persistent launch) against per-table
+"""Batched multi-table evaluation (one launch per direction) against per-table
 launches and the FP64 oracle, and its captured HIP graph replayed several
 times with the program's own work in between."""
 
@@ -61,10 +61,14 @@ def test_batch_backward_matches_per_table():
     bt = P.pwl_batch_create(tabs, offs)
     y, dx, dv = P.pwl_batch_eval_backward(bt, xt, gt)
     y, dx, dv = y.cpu().numpy(), dx.cpu().numpy(), dv.cpu().numpy()
+    # without y and dx (dL/dv is summed from per-workgroup partials with FP32
+    # atomics, so two calls agree to the error bound, not bit for bit)
+    _, _, dv2 = P.pwl_batch_eval_backward(bt, xt, gt, want=())
+    dv2 = dv2.cpu().numpy()
     for i, (t, o0, o1) in enumerate(zip(tabs, offs[:-1], offs[1:])):
         d0, d1 = bt.dv_offsets[i], bt.dv_offsets[i + 1]
         if o1 == o0:
-            assert np.all(dv[d0:d1] == 0.0)
+            assert np.all(dv[d0:d1] == 0.0) and np.all(dv2[d0:d1] == 0.0)
             continue
         y1, dx1, dv1 = P.pwl_eval_backward(t, xt[o0:o1], gt[o0:o1])
         assert np.array_equal(y[o0:o1], y1.cpu().numpy())
@@ -76,9 +80,7 @@ def test_batch_backward_matches_per_table():
         _, _, wk = O.evaluate_backward(X, np.zeros(len(X)), x[o0:o1].astype(np.float64),
                                        np.abs(g[o0:o1]).astype(np.float64))
         assert np.all(np.abs(dv[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30)
-    # without y and dx
-    _, _, dv2 = P.pwl_batch_eval_backward(bt, xt, gt, want=())
-    assert np.allclose(dv2.cpu().numpy(), dv, rtol=1e-5, atol=1e-5)
+        assert np.all(np.abs(dv2[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30)
     bt.free()
 
 
@@ -149,24 +151,28 @@ def test_batch_misaligned_and_degenerate_shapes():
     bt.free()
 
 
-def test_batch_two_lds_classes():
-    """With two workgroups per CU, N = 4096 tables need more LDS than that
-    allows, so they get a launch of their own next to the small tables; both
-    launches match the per-table evaluator bit for bit (y, dx) and dL/dv
-    matches the oracle, with the two classes interleaved in table order."""
+@pytest.mark.parametrize("shapes", [((2, 1024, 16), (1, 1024, 16)), ((4, 1024, 1), (2, 512, 1))],
+                         ids=["16-per-CU", "1-per-CU"])
+def test_batch_mixed_table_sizes(shapes):
+    """Tables of very different LDS footprints (N = 4096, 64, 1000), each
+    appearing several times, on a grid of 16 workgroups per CU (many rounds,
+    every workgroup reserving the largest table's LDS) and of one: the grid is
+    the configured workgroups per CU, y and dx match the per-table evaluator
+    bit for bit and dL/dv matches the oracle."""
     import paper_1510_02975_amd as P
     library()
     dev = device()
-    P.pwl_set_launch(P.KERNEL_BATCH, 2, 1024, 2)
-    P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, 2, 1024, 2)
+    P.pwl_set_launch(P.KERNEL_BATCH, *shapes[0])
+    P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, *shapes[1])
     try:
-        _two_classes(P, dev)
+        _mixed_sizes(P, dev, shapes)
     finally:
         P.pwl_set_launch(P.KERNEL_BATCH, 0, 0, 0)
         P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, 0, 0, 0)
 
 
-def _two_classes(P, dev):
+def _mixed_sizes(P, dev, shapes):
+    num_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     big = P.pwl_build(O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, O.PROJ)
     small = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 64, O.UNIFORM, O.INTERP)
     mid = P.pwl_build(O.BESSEL_J0, (1.0,), 0.0, 50.0, 1000, O.OPTIMAL, O.INTERP)
@@ -178,11 +184,8 @@ def _two_classes(P, dev):
     g = W.upstream_grad(n, 6)
     xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
     bt = P.pwl_batch_create(tabs, offs)
-    one = P.pwl_batch_create([small], [0, 5])
-    say("two classes: grid %d (one small class alone: %d), runs %d" % (bt.grid_fwd, one.grid_fwd, bt.runs_fwd))
-    assert bt.grid_fwd > one.grid_fwd
-    bt_grid = bt.grid_fwd
-    one.free()
+    say("grid fwd %d bwd %d, runs fwd %d bwd %d" % (bt.grid_fwd, bt.grid_bwd, bt.runs_fwd, bt.runs_bwd))
+    assert bt.grid_fwd == num_cu * shapes[0][2] and bt.grid_bwd == num_cu * shapes[1][2]
     y = P.pwl_batch_eval(bt, xt)
     yb, dxb, dvb = P.pwl_batch_eval_backward(bt, xt, gt)
     dvb = dvb.cpu().numpy()
@@ -201,11 +204,5 @@ def _two_classes(P, dev):
         _, _, wk = O.evaluate_backward(X, np.zeros(len(X)), xs, np.abs(gs))
         assert np.all(np.abs(dvb[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30), i
     bt.free()
-    # with one workgroup per CU every table fits one class
-    P.pwl_set_launch(P.KERNEL_BATCH, 4, 1024, 1)
-    b1 = P.pwl_batch_create(tabs, offs)
-    assert b1.grid_fwd < bt_grid
-    assert torch.equal(P.pwl_batch_eval(b1, xt), y)
-    b1.free()
     for t in (big, small, mid):
         t.free()
