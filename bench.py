@@ -278,7 +278,7 @@ def ingest_trace(trace_dir, out_md, command):
 
 def batch_extra(torch, P, W, dev, args):
     """Many-table workload: 4096 tables of uneven N and uneven point counts
-    (about 2^28 points in total), one persistent launch (eager and replayed
+    (about 2^28 points in total), one batched launch (eager and replayed
     from its captured graph), the fused forward+backward, and the same
     forward as one pwl_eval launch per table."""
     log("batch: building 4096 tables")

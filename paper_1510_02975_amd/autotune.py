@@ -56,7 +56,7 @@ def tune(kernel, run, candidates=None, reps=10, verbose=False):
 
 
 def tune_batch(tables, offsets, x, y, g=None, dx=None, dv=None, candidates=None, reps=5, verbose=False):
-    """Batched kernels: the persistent grids are planned when the batch is
+    """Batched kernels: the launch grids are planned when the batch is
     created, so every candidate gets its own batch.  Tunes PWL_KERNEL_BATCH
     on the forward and, when g is given, PWL_KERNEL_BATCH_BACKWARD on the
     fused backward; installs the best shapes and returns {kernel: (best, s)}."""
