@@ -162,18 +162,8 @@ __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__
 __global__ __launch_bounds__(256) void k_batch_pack(const BatchTable* __restrict__ tabs, int32_t* __restrict__ maxc) {
   const BatchTable bt = tabs[blockIdx.x];
   const EvalTable& t = bt.t;
-  const Smem s = carve(bt.img, t.N, t.K, false);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < t.N; k += nt) s.rec[k] = t.rec[k];
-  const float qnan = __builtin_nanf("");
-  for (int k = tid; k < t.N + kKnotPad; k += nt) s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
-  const int nlo = (t.K + 2) & ~1;
-  for (int u = tid; u < nlo; u += nt) s.lo[u] = (u <= t.K) ? t.lo[u] : (uint16_t)0;
-  // zero the tail of the last word
-  uint8_t* end = reinterpret_cast<uint8_t*>(s.lo + nlo);
-  uint8_t* stop = reinterpret_cast<uint8_t*>(bt.img + bt.nvec);
-  for (uint8_t* p = end + tid; p < stop; p += nt) *p = 0;
-  if (tid == 0) maxc[blockIdx.x] = (int32_t)t.meta[1];
+  stage_table(t, nullptr, carve(bt.img, t.N, t.K, false));   // the same words a kernel stages
+  if (threadIdx.x == 0) maxc[blockIdx.x] = (int32_t)t.meta[1];
 }
 
 __global__ void k_batch_zero(float* __restrict__ p, int64_t n) {

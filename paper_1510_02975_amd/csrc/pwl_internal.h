@@ -69,12 +69,18 @@ struct BuildParams {
   GaussRule gl;
 };
 
-// LDS bytes of the evaluation kernels for a table of N segments and K cells.
+// The LDS image of a table, in 16-byte words, each section starting on a
+// word: the N records, the knots with their NaN sentinels (N + kKnotPad
+// floats) and the u16 map lo[0..K], the last two rounded up to whole words.
+__host__ __device__ inline int image_knot_words(int N) { return (N + kKnotPad + 3) / 4; }
+__host__ __device__ inline int image_map_words(int K) { return (K + 1 + 7) / 8; }
+__host__ __device__ inline int image_words(int N, int K) { return N + image_knot_words(N) + image_map_words(K); }
+
+// LDS bytes of the evaluation kernels for a table of N segments and K cells:
+// the image, then (backward) the workgroup's FP64 dL/dv.
 inline size_t eval_lds_bytes(int N, int K, bool backward) {
-  // records, knots (+ sentinels), u16 map lo[0..K] padded to 4 bytes, [FP64 dL/dv]
-  size_t b = sizeof(float4) * (size_t)N + sizeof(float) * (size_t)(N + kKnotPad) +
-             sizeof(uint16_t) * (size_t)((K + 2) & ~1);
-  if (backward) b += 16 + sizeof(double) * (size_t)(N + 1);  // 16-byte aligned FP64 dL/dv
+  size_t b = 16 * (size_t)image_words(N, K);
+  if (backward) b += sizeof(double) * (size_t)(N + 1);
   return b;
 }
 

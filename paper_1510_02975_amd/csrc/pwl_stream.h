@@ -21,44 +21,84 @@ struct Smem {
   double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
 };
 
+// Sections of a table image (see image_words).  Every pointer is an offset
+// from `base` itself: a pointer rebuilt from an integer would lose its
+// address space, and LDS accesses (the dL/dv atomics above all) would go
+// through the flat path.
 __device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
   Smem s;
   s.rec = reinterpret_cast<float4*>(base);
   s.knot = reinterpret_cast<float*>(s.rec + N);
-  s.lo = reinterpret_cast<uint16_t*>(s.knot + N + kKnotPad);
-  if (backward) {
-    // 16-byte aligned by an offset from the LDS pointer itself: a pointer
-    // rebuilt from an integer would lose its address space, and the dL/dv
-    // atomics would go through the flat path instead of the LDS one
-    char* p = reinterpret_cast<char*>(s.lo + ((K + 2) & ~1));
-    s.dv = reinterpret_cast<double*>(p + ((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15));
-  } else {
-    s.dv = nullptr;
-  }
+  s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
+  s.dv = backward ? reinterpret_cast<double*>(reinterpret_cast<float4*>(s.lo) + image_map_words(K)) : nullptr;
   return s;
 }
 
-// Copy the table into LDS.  With v_override the vertex values come from the
-// caller and slopes are re-derived as (v_{k+1} - v_k) / (x_{k+1} - x_k) in
-// FP32.  The
-// knot sentinels are NaN so that every compare against them is false, even
-// for x = +inf.
-__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo,
-                                            const Smem& s) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < t.N; k += nt) {
-    float4 r = t.rec[k];
-    if (vo != nullptr) {
-      const float v0 = vo[k], v1 = vo[k + 1];
-      r.y = v0;
-      r.z = (v1 - v0) / (r.w - r.x);
-    }
-    s.rec[k] = r;
+// The words of the table's image (see image_words; the table's arrays are
+// 256-byte aligned).  A record, with v_override its value and slope
+// re-derived as (v_{k+1} - v_k) / (x_{k+1} - x_k) in FP32:
+__device__ __forceinline__ float4 record_word(const EvalTable& t, const float* __restrict__ vo, int w) {
+  float4 r = t.rec[w];
+  if (vo != nullptr) {
+    const float v0 = vo[w], v1 = vo[w + 1];
+    r.y = v0;
+    r.z = (v1 - v0) / (r.w - r.x);
   }
-  const float qnan = __builtin_nanf("");
-  for (int k = tid; k < t.N + kKnotPad; k += nt)
-    s.knot[k] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : qnan;
-  for (int u = tid; u <= t.K; u += nt) s.lo[u] = t.lo[u];
+  return r;
+}
+
+// knots 4w .. 4w+3, NaN outside the interior knots 1..N-1 (so that every
+// compare against a sentinel is false, even for x = +inf):
+__device__ __forceinline__ float4 knot_word(const EvalTable& t, int w) {
+  const int k0 = 4 * w;
+  if (k0 >= 1 && k0 + 3 <= t.N - 1) return *reinterpret_cast<const float4*>(t.knots + k0);
+  float e[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = k0 + i;
+    e[i] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : __builtin_nanf("");
+  }
+  return make_float4(e[0], e[1], e[2], e[3]);
+}
+
+// map entries 8w .. 8w+7, 0 past lo[K]:
+__device__ __forceinline__ float4 map_word(const EvalTable& t, int w) {
+  const int u0 = 8 * w;
+  if (u0 + 7 <= t.K) return *reinterpret_cast<const float4*>(t.lo + u0);
+  uint32_t p[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int u = u0 + 2 * i;
+    const uint32_t lo = (u <= t.K) ? t.lo[u] : 0u, hi = (u + 1 <= t.K) ? t.lo[u + 1] : 0u;
+    p[i] = lo | (hi << 16);
+  }
+  return make_float4(__uint_as_float(p[0]), __uint_as_float(p[1]), __uint_as_float(p[2]), __uint_as_float(p[3]));
+}
+
+// Copy the table's image to `s` (LDS, or a batch's image in global memory).
+// When every section fits in one word per thread (N no larger than the
+// workgroup), each thread loads its words before it writes any, so the copy
+// waits on one round of loads instead of one per section; the straight-line
+// form keeps the kernels' register use where the streaming loop needs it.
+__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo, const Smem& s) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nkw = image_knot_words(t.N), nmw = image_map_words(t.K);
+  float4* knot4 = reinterpret_cast<float4*>(s.knot);
+  float4* map4 = reinterpret_cast<float4*>(s.lo);
+  if (t.N <= nt && nkw <= nt && nmw <= nt) {
+    const bool hr = tid < t.N, hk = tid < nkw, hm = tid < nmw;
+    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f), k = r, m = r;
+    if (hr) r = record_word(t, vo, tid);
+    if (hk) k = knot_word(t, tid);
+    if (hm) m = map_word(t, tid);
+    if (hr) s.rec[tid] = r;
+    if (hk) knot4[tid] = k;
+    if (hm) map4[tid] = m;
+    return;
+  }
+  for (int w = tid; w < t.N; w += nt) s.rec[w] = record_word(t, vo, w);
+  for (int w = tid; w < nkw; w += nt) knot4[w] = knot_word(t, w);
+  for (int w = tid; w < nmw; w += nt) map4[w] = map_word(t, w);
 }
 
 __device__ __forceinline__ float clamp_nan(float x, float a, float b) {
