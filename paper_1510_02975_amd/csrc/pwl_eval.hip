@@ -6,9 +6,10 @@
 // non-temporal loads and stores, U vectors per thread in flight.  The path is
 // a memory-bound gather (8 bytes per point forward, 16 fused forward and
 // backward), so there is no matrix-core work: the only per-point work is the
-// map lookup, a short knot compare loop in LDS, one 16-byte record read and
-// one FMA.  The backward accumulates dL/dv in LDS with FP64 atomics and
-// writes one column of per-workgroup partial sums, which k_dv_reduce adds.
+// map lookup, a short knot compare loop in LDS, one record read (12 of its
+// 16 bytes; the backward reads all 16) and one FMA.  The backward
+// accumulates dL/dv in LDS with FP64 atomics and writes one column of
+// per-workgroup partial sums, which k_dv_reduce adds.
 // Baselines: direct FP32 evaluation of f (the device math library), expf /
 // __expf Gaussians, and a copy.
 #include <hip/hip_runtime.h>
