@@ -292,8 +292,7 @@ pwl_status pwl_batch_replay(pwl_batch* bt, void* stream);
 
 /*
  * pwl_batch_info - shape of a batch (outputs nullable): tables, points, dv
- * length, and per direction the workgroups and table runs summed over the
- * launches of one call.
+ * length, and per direction the workgroups and table runs of its launch.
  */
 pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int64_t* dv_len, int32_t* grid_fwd,
                           int32_t* grid_bwd, int32_t* runs_fwd, int32_t* runs_bwd);
