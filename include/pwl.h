@@ -189,7 +189,10 @@ pwl_status pwl_table_check(const pwl_table* t, void* stream, int32_t* flags);
 /*
  * pwl_table_info - host-side description of a table (no device access).
  * Every output pointer is nullable.  map_cells is the number of cells of the
- * uniform index map the evaluator uses to locate segments.
+ * uniform index map the evaluator uses to locate segments: 2N for a uniform
+ * partition; 4N for the optimal one, or 8N (N <= 2048) when the host
+ * predicts from f'' that 4N cells would hold three knots where they crowd.
+ * It affects speed only: the map locates exactly for any size.
  */
 pwl_status pwl_table_info(const pwl_table* t, int32_t* N, double* a, double* b, int32_t* partition,
                           int32_t* values, int32_t* map_cells);

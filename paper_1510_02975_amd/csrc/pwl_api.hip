@@ -179,6 +179,56 @@ pwl_status resolve_func(int32_t func, const double* params, int32_t nparams, pwl
   return PWL_OK;
 }
 
+// f'' on the host, only to size the index map (the device evaluates its
+// own); NaN for sampled functions, whose samples live on the device.
+double host_second(const pwl::FuncDesc& f, double x) {
+  switch (f.func) {
+    case PWL_F_GAUSSIAN: {
+      const double s2 = f.p[0] * f.p[0];
+      return f.p[1] * ((x * x) / (s2 * s2) - 1.0 / s2) * std::exp(-(x * x) / (2.0 * s2));
+    }
+    case PWL_F_LORENTZIAN: {
+      const double u = x / f.p[0], q = 1.0 + u * u;
+      return f.p[1] * (6.0 * u * u - 2.0) / (f.p[0] * f.p[0] * q * q * q);
+    }
+    case PWL_F_BESSEL_J0:
+      return (x == 0.0) ? -0.5 * f.p[0] : f.p[0] * (::j1(x) / x - ::j0(x));
+    case PWL_F_POLY: {
+      double r = 0.0;
+      for (int k = PWL_MAX_PARAMS - 1; k >= 2; --k) r = r * x + (double)(k * (k - 1)) * f.p[k];
+      return r;
+    }
+    case PWL_F_EXP:
+      return f.p[1] * f.p[0] * f.p[0] * std::exp(f.p[0] * x);
+    default:
+      return std::nan("");
+  }
+}
+
+// Map cells of a table.  The optimal partition puts about N rho(x)(b - a)/K
+// knots in the cell at x, rho the normalised density |f''|^(2/5); where that
+// exceeds 1.5 at K = 4N some cell holds three knots and every point pays a
+// third compare, so the map doubles to 8N cells (at most two knots a cell,
+// which cost the evaluator one paired read like one).  The density is
+// sampled at 512 points; the choice changes only the evaluators' speed,
+// never a result, because the map is exact for any K.
+int choose_map_cells(const pwl::BuildParams& bp, int partition) {
+  const int N = bp.N;
+  if (partition == PWL_UNIFORM) return 2 * N;
+  if (N > pwl::kWideMapMaxN) return 4 * N;
+  constexpr int kSamples = 512;
+  double sum = 0.0, peak = 0.0;
+  for (int i = 0; i < kSamples; ++i) {
+    const double x = bp.a + (bp.b - bp.a) * ((double)i + 0.5) / kSamples;
+    const double d = std::pow(std::fabs(host_second(bp.f, x)), 0.4);
+    if (!std::isfinite(d)) return 4 * N;
+    sum += d;
+    peak = std::max(peak, d);
+  }
+  if (!(sum > 0.0)) return 4 * N;
+  return (peak / (4.0 * (sum / kSamples)) > 1.5) ? 8 * N : 4 * N;
+}
+
 pwl_status resolve_build(int32_t func, const double* params, int32_t nparams, double a, double b,
                          int32_t N, int32_t partition, int32_t values, pwl::BuildParams* bp) {
   if (N < 1) return fail(PWL_EINVAL, "N must be >= 1, got %d", N);
@@ -198,7 +248,7 @@ pwl_status resolve_build(int32_t func, const double* params, int32_t nparams, do
   bp->a32 = a32;
   bp->b32 = b32;
   bp->N = N;
-  bp->K = pwl::map_cells_for(N, partition);
+  bp->K = choose_map_cells(*bp, partition);
   bp->scale32 = (float)((double)bp->K / (bp->b - bp->a));
   bp->M = pwl::kFineCellsPerSegment * N;
   bp->G = (bp->M + pwl::kDensityCellsPerBlock - 1) / pwl::kDensityCellsPerBlock;
@@ -271,11 +321,11 @@ pwl_status create_table(const pwl::BuildParams& bp, void* stream, pwl_table** ou
   pwl_status st = device_ready(&dev, nullptr, &max_lds);
   if (st != PWL_OK) return st;
   const size_t need = std::max(pwl::finalize_lds_bytes(bp.N),
-                               pwl::batch_lds_bytes(bp.N, pwl::map_cells_for(bp.N, PWL_OPTIMAL), true));
+                               pwl::batch_lds_bytes(bp.N, pwl::map_cells_max(bp.N), true));
   if (need > (size_t)max_lds)
     return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", bp.N, need, max_lds);
   pwl::TableDev td;
-  const int kcap = std::max(pwl::map_cells_for(bp.N, PWL_UNIFORM), pwl::map_cells_for(bp.N, PWL_OPTIMAL));
+  const int kcap = pwl::map_cells_max(bp.N);
   const size_t bytes = layout(&td, nullptr, bp.N, kcap, bp.G);
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, bytes);

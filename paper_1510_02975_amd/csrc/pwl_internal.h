@@ -91,7 +91,11 @@ inline size_t finalize_lds_bytes(int N) {
 
 // Number of map cells for a table of N segments: two per segment on a uniform
 // partition (each cell then holds at most one knot), four on the optimal one.
-inline int map_cells_for(int N, int partition) { return (partition == PWL_UNIFORM) ? 2 * N : 4 * N; }
+// Index-map cells: 2N for a uniform partition, 4N for the optimal one or 8N
+// where its knots crowd (chosen per table when it is built; N at most
+// kWideMapMaxN).  The allocation holds the largest map an N can get.
+constexpr int kWideMapMaxN = 2048;
+inline int map_cells_max(int N) { return N <= kWideMapMaxN ? 8 * N : 4 * N; }
 
 struct LaunchShape {
   int block;
