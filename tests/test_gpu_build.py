@@ -9,8 +9,10 @@ solve; compared with the oracle evaluated on the GPU's own FP32 knots to
 
 import numpy as np
 import pytest
+import torch
 
 import oracle as O
+import workloads as W
 from tests.gpu_util import VALUE_TOL, device, fmax_abs, library, say, ulp_diff32
 
 pytestmark = pytest.mark.gpu
@@ -135,4 +137,37 @@ def test_build_capacity_and_domain_rounding():
     t = P.pwl_build(O.GAUSSIAN, None, -0.1, 0.3, 8, O.UNIFORM, O.INTERP)
     N, a, b, part, vals, K = t.info()
     assert a == float(np.float32(-0.1)) and b == float(np.float32(0.3)) and N == 8
+    t.free()
+
+
+@pytest.mark.parametrize("case", [
+    # func, params, a, b, N, partition, expected map cells / N
+    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 1024, O.OPTIMAL, 8),   # knots crowd at 0: 2.2 per 4N-cell
+    (O.LORENTZIAN, (0.1, 1.0), -2.0, 2.0, 256, O.OPTIMAL, 8),
+    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, 4),   # 8N would not fit in LDS
+    (O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 1024, O.OPTIMAL, 4),       # 0.56 per 4N-cell
+    (O.BESSEL_J0, (1.0,), 0.0, 50.0, 1024, O.OPTIMAL, 4),
+    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 1024, O.UNIFORM, 2),
+])
+def test_map_size_per_table(case):
+    """The index map gets 8N cells where the optimal knots crowd (more than
+    1.5 predicted per 4N-cell at the density's peak, N <= 2048), 4N otherwise
+    and 2N for a uniform partition; whatever its size, the forward equals
+    the binary-search locate bit for bit on every knot and its neighbours."""
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    func, p, a, b, N, part, ratio = case
+    t = P.pwl_build(func, p, a, b, N, part, O.PROJ)
+    assert t.info()[5] == ratio * N
+    X = P.pwl_table_download(t)["knots"]
+    x = torch.from_numpy(np.concatenate([X, np.nextafter(X, np.float32(-np.inf)), np.nextafter(X, np.float32(np.inf)),
+                                         W.uniform_points(a, b, 50001, 9)]).astype(np.float32)).to(dev)
+    y = P.pwl_eval(t, x)
+    P.pwl_set_locate(P.LOCATE_SEARCH)
+    try:
+        y_bs = P.pwl_eval(t, x)
+    finally:
+        P.pwl_set_locate(P.LOCATE_MAP)
+    assert torch.equal(y, y_bs)
     t.free()
