@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Spec tolerances: outputs within 2e-6 max|f| of the FP64 oracle, table
+# Parity tolerances of the path: outputs within 2e-6 max|f| of the FP64 oracle, table
 # values within 1e-6 max|f|, gradients within 1e-5 relative.
 Y_TOL = 2e-6
 VALUE_TOL = 1e-6
