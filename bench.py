@@ -10,18 +10,25 @@ tables and three streams: step i rebuilds table i % 3 on a build stream, up
 to two steps ahead (each build waits for the evaluation that last used its
 table), and evaluates on stream i % 2 once its table is built, so that the
 tail of one evaluation overlaps the start of the next.  Every step does all
-the work.  The same steps run back to back on one stream are reported too
-("serial_step_gpoints_s"); the roofline figure is the evaluation kernel's
-own duration there, where no other kernel overlaps it.  Inputs rotate over
-three buffers and outputs over four (two steps' evaluations may run at
-once), so no step reads the previous step's cache residue.
+the work.  Inputs rotate over three buffers and outputs over four (two
+steps' evaluations may run at once), so no step reads the previous step's
+cache residue.
+
+Before anything is timed the GPU runs at least WARM_SECONDS of sustained
+steps (whatever --warmup says): it raises its clocks under load, and a short
+warm-up times the ramp.  The roofline figure is the forward kernel's own
+average duration: back-to-back launches on one stream, each between two
+fence-free HIP events.  The same steps run back to back on one stream are
+reported too ("serial_step_gpoints_s").
 
 Prints one JSON line.  Secondary figures ride along in "extra": the fused
-forward+backward on the gradient workload, direct expf, copy bandwidth, the
-Lorentzian and J0 tables at N = 256, 1024, 4096, and the many-table workload
-(one batched launch, its graph replay, the fused backward, and one launch per
-table), and the paper's sample application (per-pixel sums of Gaussian
-kernels through the table, expf and __expf).
+forward+backward on the gradient workload, direct expf, the copy ceiling,
+the Lorentzian and J0 tables at N = 256, 1024, 4096, the many-table workload
+(one batched launch, its graph replay, the fused backward, one launch per
+table from a captured graph and from a host loop, and the unscaled draw of
+the point counts), the paper's sample application (per-pixel sums of
+Gaussian kernels through a uniform and an optimal table, expf and __expf),
+and the paper's own timings with the hardware they were taken on.
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 20]
 """
@@ -43,6 +50,8 @@ HBM_PEAK_GBS = 8000.0
 FWD_BYTES_PER_POINT = 8      # x in, y out (FP32)
 FUSED_BYTES_PER_POINT = 16   # x, g in; y, dx out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_eval_fwd_gauss_n1024.json")
+WARM_SECONDS = 0.25          # sustained load before each timed phase
+CPU_THREADS_MAX = 16         # the GPU machine's CPU share for one GPU
 KERNEL_SOURCES = ["paper_1510_02975_amd/csrc/pwl_eval.hip", "paper_1510_02975_amd/csrc/pwl_stream.h",
                   "paper_1510_02975_amd/csrc/pwl_locate.h", "paper_1510_02975_amd/csrc/pwl_internal.h"]
 
@@ -120,50 +129,158 @@ class Marks:
         self.ev = []
 
 
-def timed_median(torch, fn, reps=20, warm=30, warm_seconds=0.05):
-    """Median launch time after at least `warm` untimed launches and
-    `warm_seconds` of sustained load (the GPU raises its clocks under load;
-    a short warm-up times the ramp, not the kernel)."""
+def warm_up(torch, fn, seconds=WARM_SECONDS, min_calls=0):
+    """Run fn(i) until `seconds` of sustained load have passed (and at least
+    min_calls calls); returns the seconds spent.  The GPU raises its clocks
+    under sustained load: a short warm-up times the ramp, not the kernel."""
     t0 = time.perf_counter()
     i = 0
-    while i < warm or time.perf_counter() - t0 < warm_seconds:
+    while i < min_calls or time.perf_counter() - t0 < seconds:
         fn(i)
         i += 1
-        if i % 10 == 0:
+        if i % 8 == 0:
             torch.cuda.synchronize()
-    m = Marks(torch, 2 * reps)
-    for i in range(reps):
-        m.record(2 * i)
-        fn(i)
-        m.record(2 * i + 1)
     torch.cuda.synchronize()
-    t = float(np.median([m.ms(2 * i, 2 * i + 1) for i in range(reps)])) * 1e-3
+    return time.perf_counter() - t0
+
+
+def launch_durations(torch, fn, reps=20, warm_seconds=WARM_SECONDS):
+    """Durations (s) of `reps` back-to-back launches fn(0..reps-1) on the
+    current stream, each between two fence-free events, after warm_seconds
+    of sustained load."""
+    warm_up(torch, fn, warm_seconds)
+    m = Marks(torch, reps + 1)
+    for i in range(reps):
+        m.record(i)
+        fn(i)
+    m.record(reps)
+    torch.cuda.synchronize()
+    d = np.array([m.ms(i, i + 1) for i in range(reps)]) * 1e-3
     m.free()
-    return t
+    return d
 
 
-def cpu_baseline_leg(spec, x_sample, y_gpu_sample, seconds):
-    """The FP64 oracle (test infrastructure, untuned) on a bounded sample of
-    the same workload: one pass = oracle table build + evaluation of the
-    sample, repeated for about `seconds`.  Also returns the GPU output's max
-    error against the oracle on that sample."""
-    import oracle as O
-    x64 = x_sample.astype(np.float64)
+def timed_median(torch, fn, reps=20, warm_seconds=WARM_SECONDS):
+    """Median duration of back-to-back launches (see launch_durations)."""
+    return float(np.median(launch_durations(torch, fn, reps, warm_seconds)))
+
+
+def host_description():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def _oracle_rate(work, npoints, seconds):
+    """Passes of work() for about `seconds`; returns (Gpoints/s, passes, s)."""
     reps, t0 = 0, time.perf_counter()
     while True:
-        tb = O.build_table(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"],
-                           spec["partition"], spec["values"])
-        y_ref = O.evaluate(tb["X"], tb["v"], x64)
+        work()
         reps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    gpts = reps * len(x_sample) / el / 1e9
+    return reps * npoints / el / 1e9, reps, el
+
+
+def cpu_baseline_leg(spec, x_sample, y_gpu_sample, gspec, xg_sample, gg_sample, seconds):
+    """The FP64 oracle (test infrastructure, untuned) on bounded samples of
+    the workloads, on one host core and on a thread pool over chunks (NumPy
+    releases the GIL inside its array loops): forward = oracle table build +
+    evaluation of the headline sample; backward = table build + fused
+    forward and backward of the gradient workload's sample.  Also returns the
+    GPU output's max error against the oracle on the headline sample."""
+    import concurrent.futures as cf
+    import oracle as O
+    model, ncpu, avail = host_description()
+    threads = max(1, min(CPU_THREADS_MAX, avail))
+    pool = cf.ThreadPoolExecutor(threads)
+
+    def chunks(a):
+        return np.array_split(a, threads)
+
+    x64 = x_sample.astype(np.float64)
+    xc = chunks(x64)
+    last = {}
+
+    def build(sp):
+        return O.build_table(sp["func"], sp["params"], sp["a"], sp["b"], sp["N"], sp["partition"], sp["values"])
+
+    def fwd1():
+        tb = build(spec)
+        last["y"] = O.evaluate(tb["X"], tb["v"], x64)
+
+    def fwdn():
+        tb = build(spec)
+        list(pool.map(lambda c: O.evaluate(tb["X"], tb["v"], c), xc))
+
+    xg64, gg64 = xg_sample.astype(np.float64), gg_sample.astype(np.float64)
+    xgc, ggc = chunks(xg64), chunks(gg64)
+
+    def bwd1():
+        tb = build(gspec)
+        O.evaluate_backward(tb["X"], tb["v"], xg64, gg64)
+
+    def bwdn():
+        tb = build(gspec)
+        list(pool.map(lambda a: O.evaluate_backward(tb["X"], tb["v"], a[0], a[1]), zip(xgc, ggc)))
+
+    f1 = _oracle_rate(fwd1, len(x64), seconds)
+    fn = _oracle_rate(fwdn, len(x64), seconds)
+    b1 = _oracle_rate(bwd1, len(xg64), seconds)
+    bn = _oracle_rate(bwdn, len(xg64), seconds)
+    pool.shutdown()
     fmax = float(np.max(np.abs(O.f_value(spec["func"], spec["params"], np.linspace(spec["a"], spec["b"], 100001)))))
-    err = float(np.max(np.abs(y_gpu_sample.astype(np.float64) - y_ref))) / fmax
-    return {"value": gpts, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d points of the workload, table build + evaluation, %d passes in %.1f s"
-                      % (len(x_sample), reps, el)}, err
+    err = float(np.max(np.abs(y_gpu_sample.astype(np.float64) - last["y"]))) / fmax
+    return {"value": fn[0], "unit": "Gpoints/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d points of the headline workload, table build + evaluation per pass; "
+                      "%d threads over chunks: %d passes in %.1f s; one core: %.4f Gpoints/s (%d passes)"
+                      % (len(x64), threads, fn[1], fn[2], f1[0], f1[1]),
+            "value_1core": f1[0], "host_model": model, "host_cpus": ncpu, "host_cpus_available": avail,
+            "bwd": {"workload": "gradient workload (N = 512 projection), first %d points: table build + "
+                                "fused forward and backward per pass" % len(xg64),
+                    "value": bn[0], "cores": threads, "value_1core": b1[0], "unit": "Gpoints/s"}}, err
+
+
+# The paper's own timings (Table I and the application table of Sec. VI-A,
+# Sec. VI-B, Sec. VI-C): mean per-evaluation times of its synthetic benchmark
+# (Gaussian on [0, 8], N + 1 = 32 ... 512 knots) and per-pixel times of its
+# application, on an Intel Core i7-2600K (one core) and an NVIDIA GTX 580.
+# Context only: another workload on other hardware.
+def paper_figures():
+    def g(ps):
+        return round(1e3 / ps, 4)   # Gpoints/s from picoseconds per evaluation
+    knots = [32, 64, 128, 256, 512]
+    return {
+        "source": "Table I (Sec. VI-A); Sec. VI-B (Lorentzian), Sec. VI-C (J0); application table (Sec. VI-A)",
+        "hardware": {"cpu": "Intel Core i7-2600K, sequential, one core", "gpu": "NVIDIA GTX 580"},
+        "workload": "Gaussian exp(-x^2/2)/sqrt(2 pi) on [0, 8], N + 1 = 32..512 knots; per-evaluation times",
+        "gpoints_s": {
+            "cpu_expf": g(13710),
+            "cpu_uniform": [g(1780), g(1750)],
+            "cpu_optimal_by_knots": dict(zip(map(str, knots), map(g, [8900, 11230, 13830, 16910, 20120]))),
+            "gpu_expf": g(33.3),
+            "gpu_fast_expf": g(14.2),
+            "gpu_uniform_manual": [g(19.8), g(19.7)],
+            "gpu_uniform_texture": [g(7.9), g(7.8)],
+            "gpu_optimal_manual_by_knots": dict(zip(map(str, knots), map(g, [142.0, 161.9, 181.8, 203.1, 224.1]))),
+            "gpu_optimal_texture_by_knots": dict(zip(map(str, knots), map(g, [122.7, 142.9, 163.2, 188.3, 211.1]))),
+            "lorentzian_exact_cpu_gpu_gpu_fastdiv": [g(576), g(19.5), g(9.2)],
+            "j0_exact_gpu": g(78), "j0_first_asymptotic_term_gpu": g(42),
+        },
+        "application_ns_per_pixel": {"uniform_texture": 286, "fast_expf": 324, "expf": 391},
+    }
 
 
 def _kernel_rows(csv_path):
@@ -286,7 +403,9 @@ def batch_extra(torch, P, W, dev, args):
     """Many-table workload: 4096 tables of uneven N and uneven point counts
     (about 2^28 points in total), one batched launch (eager and replayed
     from its captured graph), the fused forward+backward, and the same
-    forward as one pwl_eval launch per table."""
+    forward as one pwl_eval launch per table, replayed from one captured HIP
+    graph (no host overhead) and issued from a host loop; then the same
+    tables with the unscaled draw of the point counts."""
     log("batch: building 4096 tables")
     specs = W.many_tables(T=4096, total_points=1 << args.batch_log2n, seed=2)
     tabs = [P.pwl_build(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"],
@@ -313,27 +432,66 @@ def batch_extra(torch, P, W, dev, args):
     def per_table(i):
         for t, xs, ys in views:
             P.pwl_eval(t, xs, ys)
-    t_per = timed_median(torch, per_table, reps=3, warm=1, warm_seconds=0.0)
+    t_loop = timed_median(torch, per_table, reps=3, warm_seconds=0.0)
+    # the same launches captured into one graph: replaying it costs no host time
+    gr = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        per_table(0)   # one eager pass on the capture stream first
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(gr, stream=cap, capture_error_mode="thread_local"):
+        per_table(0)
+    t_per = timed_median(torch, lambda i: gr.replay(), reps=5)
+    del gr
     table_bytes = sum(28 * s["N"] for s in specs)
+    out = {"batch_workload": "4096 tables (Gaussian/Lorentzian/J0, N log-uniform 16..4096), %d points" % n,
+           "batch_fwd_gpoints_s": n / t_fwd / 1e9,
+           "batch_fwd_hbm_frac": FWD_BYTES_PER_POINT * n / t_fwd / 1e9 / HBM_PEAK_GBS,
+           "batch_fwd_graph_gpoints_s": n / t_graph / 1e9,
+           "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9,
+           "batch_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * n / t_fb / 1e9 / HBM_PEAK_GBS,
+           "batch_per_table_launches_graph_gpoints_s": n / t_per / 1e9,
+           "batch_per_table_launches_host_loop_gpoints_s": n / t_loop / 1e9,
+           "batch_speedup_vs_per_table_graph": t_per / t_fwd,
+           "batch_grid_fwd": bt.grid_fwd, "batch_runs_fwd": bt.runs_fwd,
+           "batch_grid_bwd": bt.grid_bwd, "batch_runs_bwd": bt.runs_bwd,
+           "batch_table_bytes": table_bytes}
     bt.free()
+    del x, y, g, dx, dv, views
+    if not args.no_unscaled:
+        # the configuration's raw draw of the counts (about 2^29.2 points)
+        specs_u = W.many_tables(T=4096, seed=2, scale_to_total=False)
+        xu_h, offs_u = W.many_tables_points(specs_u, seed=0)
+        nu = int(offs_u[-1])
+        log("batch: unscaled draw, %d points" % nu)
+        xu = torch.from_numpy(xu_h).to(dev)
+        del xu_h
+        yu = torch.empty_like(xu)
+        btu = P.pwl_batch_create(tabs, offs_u)
+        tu = timed_median(torch, lambda i: P.pwl_batch_eval(btu, xu, yu), reps=5)
+        gu = torch.from_numpy(W.upstream_grad(nu, 1)).to(dev)
+        dxu = torch.empty_like(xu)
+        dvu = torch.empty(btu.dv_len, dtype=torch.float32, device=dev)
+        tub = timed_median(torch, lambda i: P.pwl_batch_eval_backward(btu, xu, gu, yu, dxu, dvu), reps=5)
+        out.update({"batch_unscaled_points": nu,
+                    "batch_unscaled_counts_min_max": [int(np.min(np.diff(offs_u))), int(np.max(np.diff(offs_u)))],
+                    "batch_unscaled_fwd_gpoints_s": nu / tu / 1e9,
+                    "batch_unscaled_fwd_hbm_frac": FWD_BYTES_PER_POINT * nu / tu / 1e9 / HBM_PEAK_GBS,
+                    "batch_unscaled_fwd_bwd_gpoints_s": nu / tub / 1e9,
+                    "batch_unscaled_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * nu / tub / 1e9 / HBM_PEAK_GBS})
+        btu.free()
+        del xu, yu, gu, dxu, dvu
     for t in tabs:
         t.free()
-    return {"batch_workload": "4096 tables (Gaussian/Lorentzian/J0, N log-uniform 16..4096), %d points" % n,
-            "batch_fwd_gpoints_s": n / t_fwd / 1e9,
-            "batch_fwd_hbm_frac": FWD_BYTES_PER_POINT * n / t_fwd / 1e9 / HBM_PEAK_GBS,
-            "batch_fwd_graph_gpoints_s": n / t_graph / 1e9,
-            "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9,
-            "batch_fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * n / t_fb / 1e9 / HBM_PEAK_GBS,
-            "batch_per_table_launches_gpoints_s": n / t_per / 1e9,
-            "batch_grid_fwd": bt.grid_fwd, "batch_runs_fwd": bt.runs_fwd,
-            "batch_table_bytes": table_bytes}
+    return out
 
 
 def c3_extra(torch, P, W, dev):
     """Lorentzian on [-20, 20] and J0 on [0, 50], optimal partition, N in
     {256, 1024, 4096}, projection values, 2^27 uniform points: forward
-    throughput per table size (the LDS footprint grows with N), and the same
-    functions evaluated directly (no table)."""
+    throughput per table size (the LDS footprint grows with N)."""
     out = {}
     for spec in (W.LORENTZ, W.BESSEL):
         n = spec["n"]
@@ -348,9 +506,6 @@ def c3_extra(torch, P, W, dev):
             out[key + "_gpoints_s"] = n / s / 1e9
             out[key + "_hbm_frac"] = FWD_BYTES_PER_POINT * n / s / 1e9 / HBM_PEAK_GBS
             t.free()
-        # the same function evaluated directly with the device math library
-        s = timed_median(torch, lambda i: P.pwl_direct_eval(spec["func"], spec["params"], xs[i % 2], ys[i % 2]))
-        out["direct_%s_gpoints_s" % spec["name"].split("_")[0]] = n / s / 1e9
         del xs, ys
     return out
 
@@ -358,22 +513,65 @@ def c3_extra(torch, P, W, dev):
 def kde_extra(torch, P, W, dev):
     """The sample application (per-pixel sums of Gaussian kernels, T = 16
     reference frames, 5 x 5 windows: 1200 kernel values per pixel) at CIF
-    and 1080p, with the kernel through a table of exp(-u^2/2) on [0, 8]
-    (optimal, N = 1024, projection), expf and __expf: mean time per pixel."""
+    and 1080p, with the kernel through a table of exp(-u^2/2) on [0, 8] -
+    uniform partition (the paper's choice for this application), N = 64 and
+    1024, and the optimal partition, N = 1024 - and through expf and __expf:
+    mean time per pixel."""
     c = W.KDE_CIF
-    t = P.pwl_build(0, (1.0, 1.0), 0.0, 8.0, 1024, 1, 1)
+    tables = {"table_uniform_n64": P.pwl_build(0, (1.0, 1.0), 0.0, 8.0, 64, 0, 1),
+              "table_uniform_n1024": P.pwl_build(0, (1.0, 1.0), 0.0, 8.0, 1024, 0, 1),
+              "table_optimal_n1024": P.pwl_build(0, (1.0, 1.0), 0.0, 8.0, 1024, 1, 1)}
     out = {}
     for label, H, Wd in (("cif", c["H"], c["W"]), ("1080p", 1080, 1920)):
         f_h, h_h = W.kde_frames(H, Wd, c["T"], seed=4)
         f, h = torch.from_numpy(f_h).to(dev), torch.from_numpy(h_h).to(dev)
         y = torch.empty((H, Wd), dtype=torch.float32, device=dev)
-        for name, mode in (("table", P.KDE_TABLE), ("expf", P.KDE_EXPF), ("fast_expf", P.KDE_FAST_EXPF)):
+        runs = [(name, P.KDE_TABLE, t) for name, t in tables.items()]
+        runs += [("expf", P.KDE_EXPF, None), ("fast_expf", P.KDE_FAST_EXPF, None)]
+        for name, mode, t in runs:
             s = timed_median(torch, lambda i: P.pwl_kde(t, mode, f, h, c["radius"], c["sigma"], y), reps=10)
             out["kde_%s_%s_ns_per_pixel" % (label, name)] = s / (H * Wd) * 1e9
         del f, h, y
-    t.free()
+    for t in tables.values():
+        t.free()
     out["kde_kernel_values_per_pixel"] = 3 * c["T"] * (2 * c["radius"] + 1) ** 2
     return out
+
+
+def fused_extra(torch, P, W, dev):
+    """Fused forward + backward on the gradient workload (N = 512 projection,
+    2^26 points, x and g ~ N(0, 1)): the library's launch shape and a few
+    others timed in the same run."""
+    gs = dict(W.GRAD)
+    ng = gs["n"]
+    xg_h, gg_h = W.grad_inputs(ng)
+    tg = P.pwl_build(gs["func"], gs["params"], gs["a"], gs["b"], gs["N"], gs["partition"], gs["values"])
+    xg = [torch.from_numpy(xg_h).to(dev) for _ in range(2)]
+    gg = [torch.from_numpy(gg_h).to(dev) for _ in range(2)]
+    yg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
+    dxg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
+    dvg = torch.empty(gs["N"] + 1, dtype=torch.float32, device=dev)
+    fb = lambda i: P.pwl_eval_backward(tg, xg[i % 2], gg[i % 2], yg[i % 2], dxg[i % 2], dvg)
+    lib_shape = P.pwl_get_launch(P.KERNEL_BACKWARD)
+    shapes = {}
+    for shape in (lib_shape, (2, 512, 2), (2, 256, 4), (4, 1024, 1)):
+        P.pwl_set_launch(P.KERNEL_BACKWARD, *shape)
+        shapes["x".join(str(v) for v in shape)] = timed_median(torch, fb)
+    P.pwl_set_launch(P.KERNEL_BACKWARD, *lib_shape)
+    default = "x".join(str(v) for v in lib_shape)
+    d = launch_durations(torch, fb, reps=20)
+    t_fb = float(np.mean(d))
+    best = min(shapes, key=shapes.get)
+    out = {"fwd_bwd_workload": "gauss_optimal_n512_proj, 2^26 points x~N(0,1), g~N(0,1)",
+           "fwd_bwd_gpoints_s": ng / t_fb / 1e9,
+           "fwd_bwd_hbm_frac": FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS,
+           "fwd_bwd_us_mean": t_fb * 1e6,
+           "fwd_bwd_launch": default, "fwd_bwd_best_launch": best,
+           "fwd_bwd_best_gpoints_s": ng / shapes[best] / 1e9,
+           "fwd_bwd_us_by_launch": {k: v * 1e6 for k, v in shapes.items()}}
+    del xg, gg, yg, dxg
+    tg.free()
+    return out, xg_h, gg_h
 
 
 def main():
@@ -388,13 +586,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-unscaled", action="store_true")
     ap.add_argument("--batch-log2n", type=int, default=28)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -460,19 +659,20 @@ def main():
         main.wait_stream(other)
         main.wait_stream(side)
 
-    def serial_steps(steps, marks=None):
+    def serial_steps(steps):
         for i in range(steps):
-            if marks:
-                marks.record(2 * i, main)
             rebuild(tables[0], main)
-            if marks:
-                marks.record(2 * i + 1, main)
             P.pwl_eval(tables[0], xs[i % sets], ys[i % sets], stream=main)
-        if marks:
-            marks.record(2 * steps, main)
 
-    log("warmup %d" % args.warmup)
+    # warm-up: --warmup steps, and at least WARM_SECONDS of them
+    log("warmup: %d steps and at least %.2f s" % (args.warmup, WARM_SECONDS))
+    t0 = time.perf_counter()
     run_steps(args.warmup)
+    torch.cuda.synchronize()
+    while time.perf_counter() - t0 < WARM_SECONDS:
+        run_steps(max(4, args.warmup))
+        torch.cuda.synchronize()
+    warm_s = time.perf_counter() - t0
     for t in tables:
         assert P.pwl_table_check(t) == 0
     torch.cuda.synchronize()
@@ -486,86 +686,77 @@ def main():
     wall = t1 - t0
     m_cpu = min(n, 1 << args.cpu_sample_log2)
     y_sample = ys[(args.steps - 1) % len(ys)][:m_cpu].cpu().numpy()   # before anything reuses ys
-    # the same steps without the overlap, for reference
-    serial_steps(args.warmup)
-    smarks = Marks(torch, 2 * args.steps + 1)
+    # the same steps on one stream, for reference
+    warm_up(torch, lambda i: serial_steps(1))
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
-    serial_steps(args.steps, smarks)
+    serial_steps(args.steps)
     torch.cuda.synchronize()
     serial_wall = time.perf_counter() - ts0
-    # build time of a step when nothing else runs (the serial reference)
-    build_s = float(np.mean([smarks.ms(2 * i, 2 * i + 1) for i in range(args.steps)])) * 1e-3
-    # the evaluation kernel alone: its launches in the serial steps, where
-    # nothing overlaps them (pipelined launches share the GPU with each other)
-    eval_s = float(np.mean([smarks.ms(2 * i + 1, 2 * i + 2) for i in range(args.steps)])) * 1e-3
-    smarks.free()
+    # the forward kernel alone: back-to-back launches on one stream
+    reps = max(20, args.steps)
+    d_eval = launch_durations(torch, lambda i: P.pwl_eval(tables[0], xs[i % sets], ys[i % len(ys)]), reps=reps)
+    eval_s = float(np.mean(d_eval))
+    # the build alone (all its kernels, one stream)
+    d_build = launch_durations(torch, lambda i: rebuild(tables[0], main), reps=20)
+    build_s = float(np.mean(d_build))
     value = n * args.steps / wall / 1e9
     achieved = FWD_BYTES_PER_POINT * n / eval_s / 1e9
     log("step %.3f ms, eval kernel %.1f us (%.0f GB/s), build %.1f us"
         % (wall / args.steps * 1e3, eval_s * 1e6, achieved, build_s * 1e6))
     traffic = measured_traffic()
 
-    extra = {"eval_kernel_us": eval_s * 1e6, "build_us": build_s * 1e6,
+    extra = {"warmup_seconds": warm_s,
+             "eval_kernel_us": eval_s * 1e6, "eval_kernel_us_median": float(np.median(d_eval)) * 1e6,
+             "eval_kernel_launches_timed": reps, "build_us": build_s * 1e6,
              "eval_only_gpoints_s": n / eval_s / 1e9,
              "pipelined_step_us": wall / args.steps * 1e6,
              "serial_step_gpoints_s": n * args.steps / serial_wall / 1e9,
-             "kernel_source_hash": kernel_source_hash()}
-    # the copy kernel: the practical HBM ceiling, and the byte-counter calibration
-    t_copy = timed_median(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % sets]))
-    extra["copy_GBs"] = 8.0 * n / t_copy / 1e9
+             "kernel_source_hash": kernel_source_hash(),
+             "launch": {"forward": P.pwl_get_launch(P.KERNEL_FORWARD),
+                        "backward": P.pwl_get_launch(P.KERNEL_BACKWARD),
+                        "batch_forward": P.pwl_get_launch(P.KERNEL_BATCH),
+                        "batch_backward": P.pwl_get_launch(P.KERNEL_BATCH_BACKWARD),
+                        "locate": "search" if P.pwl_get_locate() == P.LOCATE_SEARCH else "map",
+                        "tuned_from": P.binding.TUNED_SOURCE}}
+    # the copy kernel in the forward's launch shape: the practical HBM ceiling
+    d_copy = launch_durations(torch, lambda i: P.pwl_copy(xs[i % sets], ys[i % len(ys)]), reps=20)
+    extra["copy_GBs"] = 8.0 * n / float(np.mean(d_copy)) / 1e9
+    extra["eval_vs_copy"] = float(np.mean(d_copy)) / eval_s
+    extra["paper"] = paper_figures()
+    xg_h = gg_h = None
     if not args.no_extra:
         log("extras: binary-search locate, direct expf, fused forward+backward")
         # the paper's own locate (binary search over the knots) on the same table and points
-        P.pwl_set_locate(P.LOCATE_SEARCH)
-        t_bs = timed_median(torch, lambda i: P.pwl_eval(tables[0], xs[i % sets], ys[i % sets]))
-        P.pwl_set_locate(P.LOCATE_MAP)
-        extra["locate_search_eval_us"] = t_bs * 1e6
-        extra["locate_search_gpoints_s"] = n / t_bs / 1e9
+        mode = P.pwl_get_locate()
+        P.pwl_set_locate(P.LOCATE_SEARCH if mode == P.LOCATE_MAP else P.LOCATE_MAP)
+        t_alt = timed_median(torch, lambda i: P.pwl_eval(tables[0], xs[i % sets], ys[i % sets]))
+        P.pwl_set_locate(mode)
+        alt = "search" if mode == P.LOCATE_MAP else "map"
+        extra["locate_%s_eval_us" % alt] = t_alt * 1e6
+        extra["locate_%s_gpoints_s" % alt] = n / t_alt / 1e9
         for fast in (0, 1):
             t = timed_median(torch, lambda i: P.pwl_direct_gaussian(xs[i % sets], ys[i % sets], 1.0, 1.0, fast))
             extra["direct_%s_gpoints_s" % ("fast_expf" if fast else "expf")] = n / t / 1e9
-        gs = dict(W.GRAD)
-        ng = gs["n"]
-        xg_h, gg_h = W.grad_inputs(ng)
-        tg = P.pwl_build(gs["func"], gs["params"], gs["a"], gs["b"], gs["N"], gs["partition"], gs["values"])
-        xg = [torch.from_numpy(xg_h).to(dev) for _ in range(2)]
-        gg = [torch.from_numpy(gg_h).to(dev) for _ in range(2)]
-        yg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
-        dxg = [torch.empty(ng, dtype=torch.float32, device=dev) for _ in range(2)]
-        dvg = torch.empty(gs["N"] + 1, dtype=torch.float32, device=dev)
-        fb = lambda i: P.pwl_eval_backward(tg, xg[i % 2], gg[i % 2], yg[i % 2], dxg[i % 2], dvg)
-        # the library default and a few other launch shapes, timed in this run
-        shapes = {}
-        for shape in (None, (2, 512, 2), (2, 512, 4), (2, 256, 4), (4, 1024, 1)):
-            P.pwl_set_launch(P.KERNEL_BACKWARD, *(shape or (0, 0, 0)))
-            key = "x".join(str(v) for v in P.pwl_get_launch(P.KERNEL_BACKWARD))
-            shapes[key] = timed_median(torch, fb)
-        P.pwl_set_launch(P.KERNEL_BACKWARD, 0, 0, 0)
-        default = "x".join(str(v) for v in P.pwl_get_launch(P.KERNEL_BACKWARD))
-        t_fb = shapes[default]
-        best = min(shapes, key=shapes.get)
-        extra["fwd_bwd_workload"] = "gauss_optimal_n512_proj, 2^26 points x~N(0,1), g~N(0,1)"
-        extra["fwd_bwd_gpoints_s"] = ng / t_fb / 1e9
-        extra["fwd_bwd_hbm_frac"] = FUSED_BYTES_PER_POINT * ng / t_fb / 1e9 / HBM_PEAK_GBS
-        extra["fwd_bwd_launch"] = default
-        extra["fwd_bwd_best_launch"] = best
-        extra["fwd_bwd_best_gpoints_s"] = ng / shapes[best] / 1e9
-        extra["fwd_bwd_us_by_launch"] = {k: v * 1e6 for k, v in shapes.items()}
-        del xg, gg, yg, dxg
-        tg.free()
+        fx, xg_h, gg_h = fused_extra(torch, P, W, dev)
+        extra.update(fx)
         log("extras: Lorentzian and J0 tables, 2^27 points")
         extra.update(c3_extra(torch, P, W, dev))
         log("extras: sample application (per-pixel kernel sums)")
         extra.update(kde_extra(torch, P, W, dev))
         if not args.no_batch:
+            del xs, ys
             extra.update(batch_extra(torch, P, W, dev, args))
 
     cpu = None
     max_err = None
     if not args.no_cpu:
-        log("cpu baseline on %d points" % m_cpu)
-        cpu, max_err = cpu_baseline_leg(spec, x_host[:m_cpu], y_sample, args.cpu_seconds)
+        if xg_h is None:
+            xg_h, gg_h = W.grad_inputs(W.GRAD["n"])
+        mg = min(len(xg_h), 1 << (args.cpu_sample_log2 - 1))
+        log("cpu baseline on %d + %d points" % (m_cpu, mg))
+        cpu, max_err = cpu_baseline_leg(spec, x_host[:m_cpu], y_sample, dict(W.GRAD), xg_h[:mg], gg_h[:mg],
+                                        args.cpu_seconds)
         extra["max_err_rel_maxf_on_cpu_sample"] = max_err
 
     out = {

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define PWL_ABI_VERSION 1
+#define PWL_ABI_VERSION 2
 #define PWL_MAX_N 4096     /* segments per table: the table lives in LDS */
 #define PWL_MAX_PARAMS 6
 
@@ -84,7 +84,7 @@ typedef enum pwl_norm {
     PWL_NORM_LINF = 1   /* max over [a, b] |f - v| */
 } pwl_norm;
 
-/* Flags reported by pwl_table_check. */
+/* Build flags, reported by pwl_table_check and pwl_table_info. */
 #define PWL_FLAG_DEGENERATE 1       /* f'' == 0 everywhere: optimal partition fell back to uniform */
 #define PWL_FLAG_KNOTS_COLLAPSED 2  /* FP32 knots not strictly increasing: table unusable (NaN)    */
 #define PWL_FLAG_NONFINITE 4        /* the density integral was not finite: uniform fallback       */
@@ -187,15 +187,21 @@ pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t
 pwl_status pwl_table_check(const pwl_table* t, void* stream, int32_t* flags);
 
 /*
- * pwl_table_info - host-side description of a table (no device access).
- * Every output pointer is nullable.  map_cells is the number of cells of the
- * uniform index map the evaluator uses to locate segments: 2N for a uniform
- * partition; 4N for the optimal one, or 8N (N <= 2048) when the host
- * predicts from f'' that 4N cells would hold three knots where they crowd.
- * It affects speed only: the map locates exactly for any size.
+ * pwl_table_info - description of a table.  Every output pointer is
+ * nullable.  map_cells is the number of cells of the uniform index map the
+ * evaluator uses to locate segments: 2N for a uniform partition; 4N for the
+ * optimal one, or 8N (N <= 2048) when the host predicts from f'' that 4N
+ * cells would hold three knots where they crowd.  It affects speed only: the
+ * map locates exactly for any size.  flags receives the PWL_FLAG_* word of
+ * the table's last build (PWL_FLAG_DEGENERATE when f'' vanished and the
+ * optimal partition fell back to uniform, PWL_FLAG_KNOTS_COLLAPSED, ...):
+ * asking for it waits for that build to finish - on a library-internal
+ * stream, for an event recorded after the build, not for the caller's
+ * streams - and reads one word from the device.  Every other output is
+ * host-side and needs no device access.
  */
 pwl_status pwl_table_info(const pwl_table* t, int32_t* N, double* a, double* b, int32_t* partition,
-                          int32_t* values, int32_t* map_cells);
+                          int32_t* values, int32_t* map_cells, int32_t* flags);
 
 /*
  * pwl_table_download - copy the table to HOST buffers (each nullable):
@@ -241,8 +247,11 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
 
 /*
  * pwl_locate - the 0-based segment index i with x_i <= x < x_{i+1} of each
- * point (step 1 of Algorithm 1), after clamping to [a, b]; x = b gives N-1.
- * seg is device int32 [n].
+ * point (step 1 of Algorithm 1), after clamping to [a, b]; x = b gives N-1,
+ * NaN gives 0.  seg is device int32 [n].  It runs the very locate the
+ * evaluation kernels run for this table (the same unrolled compare depth, or
+ * the binary search when pwl_set_locate selected it), so the indices are
+ * those pwl_eval, pwl_eval_backward and the batched kernels use.
  */
 pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t n, void* stream);
 

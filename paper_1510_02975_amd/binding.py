@@ -13,6 +13,11 @@ import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpwl.so")
+# Launch shapes and locate mode chosen by the autotuner on MI355X
+# (autotune.py writes it), applied when the library is loaded; the
+# environment variable PWL_TUNED=0 keeps the library's built-in defaults.
+TUNED_PATH = os.path.join(_PKG, "tuned_mi355x.json")
+TUNED_SOURCE = None   # description of the applied tuning, or None
 
 GAUSSIAN, LORENTZIAN, BESSEL_J0, POLY, EXP, SAMPLED = 0, 1, 2, 16, 17, 32
 UNIFORM, OPTIMAL = 0, 1
@@ -52,7 +57,7 @@ _SIGNATURES = {
     "pwl_build_tol": (_c_int32, [_c_int32, _dp, _c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  _c_int32, _c_int32, _vp, ctypes.POINTER(_vp)]),
     "pwl_table_check": (_c_int32, [_vp, _vp, _ip]),
-    "pwl_table_info": (_c_int32, [_vp, _ip, _dp, _dp, _ip, _ip, _ip]),
+    "pwl_table_info": (_c_int32, [_vp, _ip, _dp, _dp, _ip, _ip, _ip, _ip]),
     "pwl_table_download": (_c_int32, [_vp, _fp, _fp, _dp, _dp, _vp]),
     "pwl_table_free": (None, [_vp]),
     "pwl_eval": (_c_int32, [_vp, _vp, _vp, _vp, _c_int64, _vp]),
@@ -95,7 +100,28 @@ def load_library(path=None):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if os.environ.get("PWL_TUNED", "1") != "0":
+        apply_tuned(TUNED_PATH)
     return lib
+
+
+def apply_tuned(path):
+    """Install the launch shapes and locate mode of an autotuner result file
+    (see autotune.save); a missing file leaves the library defaults."""
+    global TUNED_SOURCE
+    import json
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    for k, shape in rec.get("launch", {}).items():
+        _check(_lib.pwl_set_launch(int(k), *[int(v) for v in shape]))
+    if "locate" in rec:
+        _check(_lib.pwl_set_locate(int(rec["locate"])))
+    if "records" in rec:
+        _check(_lib.pwl_set_records(int(rec["records"])))
+    TUNED_SOURCE = rec.get("source", os.path.basename(path))
+    return rec
 
 
 def _check(status):
@@ -150,8 +176,14 @@ class Table:
         N, part, vals, K = _c_int32(), _c_int32(), _c_int32(), _c_int32()
         a, b = ctypes.c_double(), ctypes.c_double()
         _check(lib.pwl_table_info(self.handle, ctypes.byref(N), ctypes.byref(a), ctypes.byref(b),
-                                  ctypes.byref(part), ctypes.byref(vals), ctypes.byref(K)))
+                                  ctypes.byref(part), ctypes.byref(vals), ctypes.byref(K), None))
         return N.value, a.value, b.value, part.value, vals.value, K.value
+
+    def flags(self):
+        """Build flags (PWL_FLAG_*) of the table's last build; waits for it."""
+        f = _c_int32()
+        _check(load_library().pwl_table_info(self.handle, None, None, None, None, None, None, ctypes.byref(f)))
+        return f.value
 
     def free(self):
         if self.handle is not None:

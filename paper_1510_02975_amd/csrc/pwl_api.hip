@@ -39,10 +39,14 @@ struct pwl_table {
   pwl::TableDev td;
   void* base;
   size_t bytes;
-  // dL/dv partial sums of the fused backward (one row per workgroup),
-  // allocated by the first backward call that needs more
+  hipEvent_t built = nullptr;   // recorded after every build of the table
+  // dL/dv partial sums of the fused backward (one row per workgroup), taken
+  // from the stream-ordered allocator by the first backward call that needs
+  // more; part_used is recorded after every launch that reads them
+  mutable std::mutex part_mu;
   mutable float* part = nullptr;
   mutable size_t part_cap = 0;   // floats
+  mutable hipEvent_t part_used = nullptr;
 };
 
 namespace {
@@ -71,6 +75,7 @@ pwl_status fail(pwl_status s, const char* fmt, ...) {
 constexpr int kMaxDevices = 64;
 int g_num_cu[kMaxDevices];
 int g_max_lds[kMaxDevices];
+hipStream_t g_aux[kMaxDevices];   // library-internal stream for small host reads
 std::once_flag g_cfg_once[kMaxDevices];
 hipError_t g_cfg_err[kMaxDevices];
 
@@ -86,6 +91,7 @@ pwl_status device_ready(int* dev_out, int* num_cu, int* max_lds = nullptr) {
     if (e == hipSuccess) e = pwl::configure_eval_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_batch_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_kde_kernels(lds);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g_aux[dev], hipStreamNonBlocking);
     g_num_cu[dev] = cu > 0 ? cu : 1;
     g_max_lds[dev] = lds;
     g_cfg_err[dev] = e;
@@ -313,6 +319,8 @@ int32_t pwl_abi_version(void) { return PWL_ABI_VERSION; }
 
 const char* pwl_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
 namespace {
 
 // Allocates a table for resolved build parameters and enqueues its build.
@@ -332,8 +340,11 @@ pwl_status create_table(const pwl::BuildParams& bp, void* stream, pwl_table** ou
   if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   layout(&td, static_cast<char*>(base), bp.N, kcap, bp.G);
   pwl_table* t = new pwl_table{dev, kcap, bp, td, base, bytes};
-  e = pwl::launch_build(t->bp, t->td, static_cast<hipStream_t>(stream));
+  e = hipEventCreateWithFlags(&t->built, hipEventDisableTiming);
+  if (e == hipSuccess) e = pwl::launch_build(t->bp, t->td, static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = hipEventRecord(t->built, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
+    if (t->built) (void)hipEventDestroy(t->built);
     (void)hipFree(base);
     delete t;
     return fail(PWL_EHIP, "build launch failed: %s", hipGetErrorString(e));
@@ -343,6 +354,8 @@ pwl_status create_table(const pwl::BuildParams& bp, void* stream, pwl_table** ou
 }
 
 }  // namespace
+
+extern "C" {
 
 pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double a, double b, int32_t N,
                      int32_t partition, int32_t values, void* stream, pwl_table** out) {
@@ -354,6 +367,8 @@ pwl_status pwl_build(int32_t func, const double* params, int32_t nparams, double
   return create_table(bp, stream, out);
 }
 
+}  // extern "C"
+
 namespace {
 
 // Fine cells for the prediction integrals: the density has |x - z|^(2/5)
@@ -362,6 +377,8 @@ namespace {
 constexpr int kNormCells = 1 << 20;
 
 }  // namespace
+
+extern "C" {
 
 pwl_status pwl_plan_tol(int32_t func, const double* params, int32_t nparams, double a, double b, double tol,
                         int32_t norm, int32_t values, void* stream, int32_t* N_out, int32_t* partition_out,
@@ -451,6 +468,8 @@ pwl_status pwl_build_sampled(const double* f, const double* f2, int32_t S, doubl
 pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t nparams, double a,
                        double b, int32_t partition, int32_t values, void* stream) {
   if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (t->bp.f.func == PWL_F_SAMPLED)
+    return fail(PWL_EINVAL, "a table built from samples cannot be rebuilt: build a new one");
   pwl::BuildParams bp;
   pwl_status st = resolve_build(func, params, nparams, a, b, t->bp.N, partition, values, &bp);
   if (st != PWL_OK) return st;
@@ -460,6 +479,7 @@ pwl_status pwl_rebuild(pwl_table* t, int32_t func, const double* params, int32_t
   if (st != PWL_OK) return st;
   t->bp = bp;
   PWL_HIP(pwl::launch_build(t->bp, t->td, static_cast<hipStream_t>(stream)));
+  PWL_HIP(hipEventRecord(t->built, static_cast<hipStream_t>(stream)));
   return PWL_OK;
 }
 
@@ -477,8 +497,20 @@ pwl_status pwl_table_check(const pwl_table* t, void* stream, int32_t* flags) {
 }
 
 pwl_status pwl_table_info(const pwl_table* t, int32_t* N, double* a, double* b, int32_t* partition,
-                          int32_t* values, int32_t* map_cells) {
+                          int32_t* values, int32_t* map_cells, int32_t* flags) {
   if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (flags) {
+    // the flags of the table's last build: the library's own stream waits
+    // for that build only (an event recorded after it), then reads the word
+    pwl_status st = check_table(t, nullptr);
+    if (st != PWL_OK) return st;
+    uint32_t host = 0;
+    hipStream_t aux = g_aux[t->device];
+    PWL_HIP(hipStreamWaitEvent(aux, t->built, 0));
+    PWL_HIP(hipMemcpyAsync(&host, t->td.status, sizeof(host), hipMemcpyDeviceToHost, aux));
+    PWL_HIP(hipStreamSynchronize(aux));
+    *flags = (int32_t)host;
+  }
   if (N) *N = t->bp.N;
   if (a) *a = t->bp.a;
   if (b) *b = t->bp.b;
@@ -506,8 +538,15 @@ pwl_status pwl_table_download(const pwl_table* t, float* knots, float* values, d
 
 void pwl_table_free(pwl_table* t) {
   if (t == nullptr) return;
+  if (t->part != nullptr) {
+    // stream-ordered memory: released after its last user, then waited for
+    (void)hipEventSynchronize(t->part_used);
+    (void)hipFreeAsync(t->part, g_aux[t->device]);
+    (void)hipStreamSynchronize(g_aux[t->device]);
+  }
+  if (t->part_used) (void)hipEventDestroy(t->part_used);
+  if (t->built) (void)hipEventDestroy(t->built);
   (void)hipFree(t->base);
-  if (t->part != nullptr) (void)hipFree(t->part);
   delete t;
 }
 
@@ -536,26 +575,34 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
   pwl_status st = check_table(t, &num_cu);
   if (st != PWL_OK) return st;
   const pwl::EvalTable e = eval_view(t);
-  if (dv != nullptr && n > 0) {
-    const size_t need = pwl::backward_workspace_floats(e, x, g, y, dx, n, num_cu);
-    if (need > t->part_cap) {
-      if (t->part != nullptr) {
-        PWL_HIP(hipDeviceSynchronize());   // a previous call may still read the old rows
-        (void)hipFree(t->part);
-        t->part = nullptr;
-        t->part_cap = 0;
-      }
-      void* p = nullptr;
-      hipError_t me = hipMalloc(&p, need * sizeof(float));
-      if (me != hipSuccess)
-        return fail(PWL_ENOMEM, "hipMalloc(%zu) for the dL/dv partial sums failed: %s", need * sizeof(float),
-                    hipGetErrorString(me));
-      t->part = static_cast<float*>(p);
-      t->part_cap = need;
-    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dv == nullptr || n == 0) {
+    PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, nullptr, n, num_cu, s));
+    return PWL_OK;
   }
-  PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, t->part, n, num_cu,
-                                    static_cast<hipStream_t>(stream)));
+  // The partial-sum rows: grown in stream order on the caller's stream (the
+  // old rows are released once their last user - on whatever stream - has
+  // finished), never by a device-wide synchronisation.
+  std::lock_guard<std::mutex> lock(t->part_mu);
+  const size_t need = pwl::backward_workspace_floats(e, x, g, y, dx, n, num_cu);
+  if (need > t->part_cap) {
+    if (t->part != nullptr) {
+      PWL_HIP(hipStreamWaitEvent(s, t->part_used, 0));
+      PWL_HIP(hipFreeAsync(t->part, s));
+      t->part = nullptr;
+      t->part_cap = 0;
+    }
+    if (t->part_used == nullptr) PWL_HIP(hipEventCreateWithFlags(&t->part_used, hipEventDisableTiming));
+    void* p = nullptr;
+    hipError_t me = hipMallocAsync(&p, need * sizeof(float), s);
+    if (me != hipSuccess)
+      return fail(PWL_ENOMEM, "hipMallocAsync(%zu) for the dL/dv partial sums failed: %s", need * sizeof(float),
+                  hipGetErrorString(me));
+    t->part = static_cast<float*>(p);
+    t->part_cap = need;
+  }
+  PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, t->part, n, num_cu, s));
+  PWL_HIP(hipEventRecord(t->part_used, s));
   return PWL_OK;
 }
 
@@ -632,6 +679,8 @@ pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const vo
 }
 
 // ---- batches ---------------------------------------------------------------
+
+}  // extern "C"
 
 namespace {
 
@@ -717,6 +766,8 @@ ClassPlan plan_batch(const pwl_table* const* tables, int T, const int64_t* offse
 }
 
 }  // namespace
+
+extern "C" {
 
 pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
                             pwl_batch** out) {
@@ -822,6 +873,8 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   return PWL_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 pwl_status check_batch(const pwl_batch* bt) {
@@ -846,6 +899,8 @@ pwl_status check_batch_args(const pwl_batch* bt, const float* x, const float* g,
 }
 
 }  // namespace
+
+extern "C" {
 
 pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream) {
   pwl_status st = check_batch(bt);

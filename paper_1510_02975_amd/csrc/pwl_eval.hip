@@ -125,15 +125,36 @@ __global__ __launch_bounds__(kReduceThreads) void k_dv_reduce(const float* __res
   if (lane == 0) dv[k] = (float)s;
 }
 
+// Segment indices through the same locate the evaluation kernels run: the
+// unrolled compare depth chosen from meta[1] (or the binary search), so the
+// indices this returns are the ones k_eval_fwd, k_eval_bwd and the batched
+// kernels use.
+template <int MAXC>
+__device__ __forceinline__ void locate_all(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+                                           int32_t* __restrict__ seg, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    seg[i] = locate<MAXC>(x[i], t, s);
+}
+
 __global__ __launch_bounds__(1024) void k_locate(EvalTable t, const float* __restrict__ x,
-                                                 int32_t* __restrict__ seg, int64_t n) {
+                                                 int32_t* __restrict__ seg, int64_t n, int flags) {
   extern __shared__ float4 lds_f4[];
   const Smem s = carve(lds_f4, t.N, t.K, false);
   stage_table(t, nullptr, s);
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    seg[i] = locate_any(x[i], t, s);
+  if (flags & 2) {   // PWL_LOCATE_SEARCH
+    locate_all<-1>(t, s, x, seg, n);
+    return;
+  }
+  switch (t.meta[1]) {
+    case 0:
+    case 1: locate_all<1>(t, s, x, seg, n); break;
+    case 2: locate_all<2>(t, s, x, seg, n); break;
+    case 3: locate_all<3>(t, s, x, seg, n); break;
+    case 4: locate_all<4>(t, s, x, seg, n); break;
+    default: locate_all<0>(t, s, x, seg, n); break;
+  }
 }
 
 __global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
@@ -398,7 +419,8 @@ LaunchShape baseline_shape(int64_t n4, int64_t n, int num_cu) {
 hipError_t launch_locate(const EvalTable& t, const float* x, int32_t* seg, int64_t n, int num_cu,
                          hipStream_t s) {
   const LaunchShape ls = stream_shape(g_launch[0], eval_lds_bytes(t.N, t.K, false), 0, n, num_cu);
-  hipLaunchKernelGGL(k_locate, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, x, seg, n);
+  const int v = (g_locate == PWL_LOCATE_SEARCH) ? 2 : 0;
+  hipLaunchKernelGGL(k_locate, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, x, seg, n, v);
   return hipGetLastError();
 }
 

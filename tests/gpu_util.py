@@ -51,3 +51,33 @@ def ulp_diff32(a, b):
     ia = np.where(ia < 0, -(ia & 0x7FFFFFFF), ia)
     ib = np.where(ib < 0, -(ib & 0x7FFFFFFF), ib)
     return np.abs(ia - ib)
+
+
+class locate_mode:
+    """Run a block with pwl_set_locate(mode), then restore the mode in force
+    before (the library may run a tuned mode, not the default)."""
+
+    def __init__(self, P, mode):
+        self.P, self.mode = P, mode
+
+    def __enter__(self):
+        self.prev = self.P.pwl_get_locate()
+        self.P.pwl_set_locate(self.mode)
+
+    def __exit__(self, *exc):
+        self.P.pwl_set_locate(self.prev)
+
+
+class launch_shape:
+    """Run a block with pwl_set_launch(kernel, *shape), then restore the
+    shape in force before."""
+
+    def __init__(self, P, kernel, shape):
+        self.P, self.kernel, self.shape = P, kernel, shape
+
+    def __enter__(self):
+        self.prev = self.P.pwl_get_launch(self.kernel)
+        self.P.pwl_set_launch(self.kernel, *self.shape)
+
+    def __exit__(self, *exc):
+        self.P.pwl_set_launch(self.kernel, *self.prev)

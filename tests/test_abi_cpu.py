@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert library().pwl_abi_version() == 1
+    assert library().pwl_abi_version() == 2
 
 
 def _build(lib, func=0, params=None, n=0, a=-1.0, b=1.0, N=8, part=1, vals=1):
@@ -77,7 +77,7 @@ def test_calls_on_null_table_are_rejected():
     assert lib.pwl_eval(None, None, None, None, 10, None) == -1
     assert lib.pwl_eval_backward(None, None, None, None, None, None, None, 10, None) == -1
     assert lib.pwl_locate(None, None, None, 10, None) == -1
-    assert lib.pwl_table_info(None, None, None, None, None, None, None) == -1
+    assert lib.pwl_table_info(None, None, None, None, None, None, None, None) == -1
     assert lib.pwl_table_check(None, None, None) == -1
     assert lib.pwl_table_download(None, None, None, None, None, None) == -1
     assert lib.pwl_rebuild(None, 0, None, 0, -1.0, 1.0, 1, 1, None) == -1

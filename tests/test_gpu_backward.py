@@ -14,7 +14,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
+from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, launch_shape, library, say
 
 pytestmark = pytest.mark.gpu
 
@@ -149,12 +149,9 @@ def test_dv_is_deterministic_and_workspace_grows():
     _, _, dvr = O.evaluate_backward(X, d["values"].astype(np.float64), x64, g64)
     wk = _abs_weight(X, x64, g64)
     # more workgroups than the first calls used: the workspace is re-allocated
-    P.pwl_set_launch(P.KERNEL_BACKWARD, 1, 256, 8)
-    try:
+    with launch_shape(P, P.KERNEL_BACKWARD, (1, 256, 8)):
         _, _, dv3 = P.pwl_eval_backward(t, x, g)
-    finally:
-        P.pwl_set_launch(P.KERNEL_BACKWARD, 0, 0, 0)
-    _, _, dv4 = P.pwl_eval_backward(t, x, g)            # back to the default grid
+    _, _, dv4 = P.pwl_eval_backward(t, x, g)            # back to the library's grid
     for dv in (dv1, dv3, dv4):
         assert np.all(np.abs(dv.cpu().numpy() - dvr) <= GRAD_TOL * wk + 1e-30)
     assert torch.equal(dv4, dv1)

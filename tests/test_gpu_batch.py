@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
+from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, launch_shape, library, say
 
 pytestmark = pytest.mark.gpu
 
@@ -162,13 +162,8 @@ def test_batch_mixed_table_sizes(shapes):
     import paper_1510_02975_amd as P
     library()
     dev = device()
-    P.pwl_set_launch(P.KERNEL_BATCH, *shapes[0])
-    P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, *shapes[1])
-    try:
+    with launch_shape(P, P.KERNEL_BATCH, shapes[0]), launch_shape(P, P.KERNEL_BATCH_BACKWARD, shapes[1]):
         _mixed_sizes(P, dev, shapes)
-    finally:
-        P.pwl_set_launch(P.KERNEL_BATCH, 0, 0, 0)
-        P.pwl_set_launch(P.KERNEL_BATCH_BACKWARD, 0, 0, 0)
 
 
 def _mixed_sizes(P, dev, shapes):

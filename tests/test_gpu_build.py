@@ -13,7 +13,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import VALUE_TOL, device, fmax_abs, library, say, ulp_diff32
+from tests.gpu_util import VALUE_TOL, device, fmax_abs, library, locate_mode, say, ulp_diff32
 
 pytestmark = pytest.mark.gpu
 
@@ -90,6 +90,7 @@ def test_knot_collapse_reports_and_evaluates_to_nan():
     a = 1.0
     b = float(np.nextafter(np.nextafter(np.float32(1.0), np.float32(2)), np.float32(2)))
     t = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), a, b, 64, O.OPTIMAL, O.PROJ, check=False)
+    assert t.flags() & P.FLAG_KNOTS_COLLAPSED          # pwl_table_info waits for the build
     with pytest.raises(P.PWLError) as ei:
         P.pwl_table_check(t)
     assert ei.value.status == -4
@@ -104,6 +105,7 @@ def test_degenerate_function_falls_back_to_uniform():
     library()
     t, d, flags = _gpu_table(P, O.POLY, (1.0, -2.0), -1.0, 3.0, 40, O.OPTIMAL, O.PROJ)
     assert flags == P.FLAG_DEGENERATE
+    assert t.flags() == P.FLAG_DEGENERATE            # the same word through pwl_table_info
     U, _ = O.uniform_knots(-1.0, 3.0, 40)
     assert np.array_equal(d["knots"].astype(np.float64), U)
     assert np.max(np.abs(d["values64"] - (1.0 - 2.0 * U))) <= 1e-6
@@ -116,6 +118,7 @@ def test_rebuild_in_place_matches_fresh_build():
     device()
     t = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 256, O.UNIFORM, O.INTERP)
     P.pwl_rebuild(t, O.LORENTZIAN, (2.0, 1.5), -30.0, 30.0, O.OPTIMAL, O.PROJ)
+    assert t.flags() == 0
     assert P.pwl_table_check(t) == 0
     d1 = P.pwl_table_download(t)
     t2 = P.pwl_build(O.LORENTZIAN, (2.0, 1.5), -30.0, 30.0, 256, O.OPTIMAL, O.PROJ)
@@ -163,11 +166,9 @@ def test_map_size_per_table(case):
     X = P.pwl_table_download(t)["knots"]
     x = torch.from_numpy(np.concatenate([X, np.nextafter(X, np.float32(-np.inf)), np.nextafter(X, np.float32(np.inf)),
                                          W.uniform_points(a, b, 50001, 9)]).astype(np.float32)).to(dev)
-    y = P.pwl_eval(t, x)
-    P.pwl_set_locate(P.LOCATE_SEARCH)
-    try:
+    with locate_mode(P, P.LOCATE_MAP):
+        y = P.pwl_eval(t, x)
+    with locate_mode(P, P.LOCATE_SEARCH):
         y_bs = P.pwl_eval(t, x)
-    finally:
-        P.pwl_set_locate(P.LOCATE_MAP)
     assert torch.equal(y, y_bs)
     t.free()

@@ -1,8 +1,11 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times (library defaults): every 4096th output plus every point
-within 1e-5 of a knot is checked against the FP64 oracle's own table; size-
-independent properties (finite, within the vertex-value range) are checked on
-all outputs on the GPU."""
+benchmark times (library defaults): a strided subset of 2^24 points plus
+every point within 1e-5 of a knot is checked against the FP64 oracle -
+segment indices exactly on the GPU's own table and within 2 ulp of a knot on
+the oracle's own table, outputs within 2e-6 max|f| - and size-independent
+properties (finite, within the vertex-value range) on all outputs on the GPU.
+The many-table workload is checked on 48 sampled tables, forward and fused
+backward."""
 
 import numpy as np
 import pytest
@@ -14,14 +17,33 @@ from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
 
 pytestmark = pytest.mark.gpu
 
+SUBSET = 1 << 24
 
-def _sample_idx(x, X, stride=4096):
-    idx = np.arange(0, len(x), stride)
+
+def _sample_idx(x, X, subset=SUBSET):
+    idx = np.arange(0, len(x), max(1, len(x) // subset))
     # points near knots (the hardest segment decisions)
     pos = np.searchsorted(X, x.astype(np.float64))
     pos = np.clip(pos, 1, len(X) - 1)
     near = np.minimum(np.abs(x - X[pos]), np.abs(x - X[pos - 1])) <= 1e-5
     return np.union1d(idx, np.nonzero(near)[0][:200000])
+
+
+def _check_segments(seg, xs, Xg, Xo):
+    """Tier (ii): exactly the oracle's segments on the GPU's own knots Xg.
+    Tier (iii): on the oracle's own knots Xo, mismatches only within 2 FP32
+    ulps of a knot."""
+    x64 = xs.astype(np.float64)
+    assert np.array_equal(seg, O.locate(Xg, x64))
+    s3 = O.locate(Xo, x64)
+    diff = seg != s3
+    if diff.any():
+        xf = x64[diff]
+        pos = np.clip(np.searchsorted(Xo, xf), 1, len(Xo) - 1)
+        gap = np.minimum(np.abs(xf - Xo[pos]), np.abs(xf - Xo[pos - 1]))
+        ulp = np.spacing(np.abs(xf).astype(np.float32)).astype(np.float64)
+        assert np.all(gap <= 2 * ulp)
+    return int(diff.sum())
 
 
 def _check_forward(P, spec, x_h, label):
@@ -37,10 +59,15 @@ def _check_forward(P, spec, x_h, label):
     ref = O.build_table(spec["func"], spec["params"], spec["a"], spec["b"], spec["N"], spec["partition"],
                         spec["values"])
     idx = _sample_idx(x_h, ref["X"])
-    ys = y[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+    it = torch.from_numpy(idx).to(dev)
+    ys = y[it].cpu().numpy().astype(np.float64)
+    del y
+    seg = P.pwl_locate(t, x)[it].cpu().numpy()
+    nmis = _check_segments(seg, x_h[idx], d["knots"].astype(np.float64), ref["X"])
     yr = O.evaluate(ref["X"], ref["v"], x_h[idx].astype(np.float64))
     err = np.max(np.abs(ys - yr)) / fmax_abs(spec["func"], spec["params"], spec["a"], spec["b"])
-    say("  %s: %d points, %d sampled, max err %.3e max|f|" % (label, len(x_h), len(idx), err))
+    say("  %s: %d points, %d sampled, max err %.3e max|f|, %d index mismatches within 2 ulp of a knot"
+        % (label, len(x_h), len(idx), err, nmis))
     assert err <= Y_TOL
     t.free()
 
@@ -102,23 +129,47 @@ def test_many_tables_full_size():
     for t in tabs:
         assert P.pwl_table_check(t) == 0
     x_h, offs = W.many_tables_points(specs, seed=0)
+    n = len(x_h)
     x = torch.from_numpy(x_h).to(dev)
     bt = P.pwl_batch_create(tabs, offs)
     y = P.pwl_batch_eval(bt, x)
     assert bool(torch.isfinite(y).all())
+    g_h = W.upstream_grad(n, 1)
+    g = torch.from_numpy(g_h).to(dev)
+    yb, dx, dv = P.pwl_batch_eval_backward(bt, x, g)
+    assert torch.equal(yb, y)
+    assert bool(torch.isfinite(dx).all()) and bool(torch.isfinite(dv).all())
+    # partition of unity: every table's dL/dv sums to the sum of its g
+    dv_h = dv.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(1)
-    worst = 0.0
+    worst = worst_dx = worst_dv = 0.0
     for k in rng.choice(len(specs), 48, replace=False):
         s, o0, o1 = specs[k], int(offs[k]), int(offs[k + 1])
+        d0, d1 = bt.dv_offsets[k], bt.dv_offsets[k + 1]
         if o1 == o0:
+            assert np.all(dv_h[d0:d1] == 0.0)
             continue
+        scale = fmax_abs(s["func"], s["params"], s["a"], s["b"])
         ref = O.build_table(s["func"], s["params"], s["a"], s["b"], s["N"], s["partition"], s["values"])
         idx = np.arange(o0, o1, max(1, (o1 - o0) // 2000))
+        it = torch.from_numpy(idx).to(dev)
         yr = O.evaluate(ref["X"], ref["v"], x_h[idx].astype(np.float64))
-        err = np.max(np.abs(y[torch.from_numpy(idx).to(dev)].cpu().numpy() - yr)) / \
-            fmax_abs(s["func"], s["params"], s["a"], s["b"])
-        worst = max(worst, err)
-    say("  many tables: %d points, worst sampled err %.3e max|f|" % (len(x_h), worst))
+        worst = max(worst, np.max(np.abs(y[it].cpu().numpy() - yr)) / scale)
+        # the backward on the table's own knots and values (tier ii)
+        dd = P.pwl_table_download(tabs[k])
+        X, v = dd["knots"].astype(np.float64), dd["values"].astype(np.float64)
+        x64, g64 = x_h[o0:o1].astype(np.float64), g_h[o0:o1].astype(np.float64)
+        _, dxr, dvr = O.evaluate_backward(X, v, x64, g64)
+        _, _, wk = O.evaluate_backward(X, np.zeros(len(X)), x64, np.abs(g64))
+        assert np.all(np.abs(dv_h[d0:d1] - dvr) <= GRAD_TOL * wk + 1e-30)
+        worst_dv = max(worst_dv, float(np.max(np.abs(dv_h[d0:d1] - dvr) / np.maximum(wk, 1e-30))))
+        i = O.locate(X, x64)
+        slope = (v[i + 1] - v[i]) / (X[i + 1] - X[i])
+        dxg = dx[o0:o1].cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(dxg - dxr) <= GRAD_TOL * np.abs(g64 * slope) + 1e-30)
+        worst_dx = max(worst_dx, float(np.max(np.abs(dxg - dxr) / np.maximum(np.abs(g64 * slope), 1e-30))))
+    say("  many tables: %d points, worst sampled err %.3e max|f|, dL/dx rel %.2e, dL/dv rel %.2e"
+        % (n, worst, worst_dx, worst_dv))
     assert worst <= Y_TOL
     bt.free()
     for t in tabs:

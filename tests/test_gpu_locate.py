@@ -1,7 +1,9 @@
 """The paper's own GPU locate - a branch-free binary search over the knots
-(Sec. IV-V), here over the knots staged in LDS - against the default index
-map: both must give the same segment, so pwl_eval's outputs are
-bit-identical, on random points, every knot and its FP32 neighbours, the
+(Sec. IV-V), here over the knots staged in LDS - and the default index map,
+each against the FP64 oracle: both must return the oracle's segment index
+(Algorithm 1, step 1) on the GPU's own knots, exactly, and pwl_eval through
+either must match the oracle's evaluation; the two modes' outputs are then
+bit-identical.  Points: random, every knot and its FP32 neighbours, the
 domain ends, points outside, +-inf and NaN."""
 
 import numpy as np
@@ -10,7 +12,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import device, library, say
+from tests.gpu_util import Y_TOL, device, fmax_abs, library, locate_mode, say
 
 pytestmark = pytest.mark.gpu
 
@@ -36,16 +38,27 @@ def test_binary_search_locate_matches_index_map(spec):
     pts = [W.uniform_points(a - 1.0, b + 1.0, 100003, 3),
            X, np.nextafter(X, np.float32(-np.inf)), np.nextafter(X, np.float32(np.inf)),
            np.array([a, b, -np.inf, np.inf, np.nan, 0.0, -0.0], np.float32)]
-    x = torch.from_numpy(np.concatenate(pts).astype(np.float32)).to(dev)
-    assert P.pwl_get_locate() == P.LOCATE_MAP
-    y_map = P.pwl_eval(t, x).cpu().numpy()
-    P.pwl_set_locate(P.LOCATE_SEARCH)
-    try:
+    xh = np.concatenate(pts).astype(np.float32)
+    x = torch.from_numpy(xh).to(dev)
+    with locate_mode(P, P.LOCATE_MAP):
+        y_map = P.pwl_eval(t, x).cpu().numpy()
+        seg_map = P.pwl_locate(t, x).cpu().numpy()
+    with locate_mode(P, P.LOCATE_SEARCH):
         y_bs = P.pwl_eval(t, x).cpu().numpy()
+        seg_bs = P.pwl_locate(t, x).cpu().numpy()
         y_bs_odd = P.pwl_eval(t, x[1:4000]).cpu().numpy()   # scalar (misaligned) path
-    finally:
-        P.pwl_set_locate(P.LOCATE_MAP)
     say("  f=%d N=%d: %d points" % (func, N, x.numel()))
+    d = P.pwl_table_download(t)
+    Xg, vg = d["knots"].astype(np.float64), d["values"].astype(np.float64)
+    fin = ~np.isnan(xh)
+    ref_seg = O.locate(Xg, xh[fin].astype(np.float64))
+    assert np.array_equal(seg_map[fin], ref_seg)
+    assert np.array_equal(seg_bs[fin], ref_seg)
+    assert np.all(seg_bs[~fin] == 0) and np.all(seg_map[~fin] == 0)
+    y_ref = O.evaluate(Xg, vg, xh.astype(np.float64))
+    scale = fmax_abs(func, p, a, b)
+    assert np.array_equal(np.isnan(y_bs), np.isnan(y_ref))
+    assert np.max(np.abs(y_bs[fin] - y_ref[fin])) <= Y_TOL * scale
     assert np.array_equal(y_map, y_bs, equal_nan=True)
     assert np.array_equal(y_map[1:4000], y_bs_odd, equal_nan=True)
     t.free()

@@ -77,5 +77,10 @@ def test_samples_of_the_gaussian_give_the_gaussian_table():
     d = float((P.pwl_eval(ts, x) - P.pwl_eval(tf, x)).abs().max())
     say("  sampled vs analytic Gaussian tables: max |dy| = %.2e" % d)
     assert d <= 2 * Y_TOL
+    # a table from samples cannot be rebuilt as an analytic one
+    with pytest.raises(P.PWLError) as ei:
+        P.pwl_rebuild(ts, O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, O.OPTIMAL, O.PROJ)
+    assert ei.value.status == -1
+    assert float((P.pwl_eval(ts, x) - P.pwl_eval(tf, x)).abs().max()) == d   # unchanged
     ts.free()
     tf.free()

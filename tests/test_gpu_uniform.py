@@ -13,7 +13,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, say
+from tests.gpu_util import GRAD_TOL, Y_TOL, device, fmax_abs, library, locate_mode, say
 
 pytestmark = pytest.mark.gpu
 
@@ -47,13 +47,11 @@ def test_uniform_tables_at_segment_ends(spec, vals):
     X = d["knots"]
     x_h = _points(X, np.float32(a), np.float32(b), 11)
     x = torch.from_numpy(x_h).to(dev)
-    y = P.pwl_eval(t, x).cpu().numpy()
-    y_odd = P.pwl_eval(t, x[1:5001]).cpu().numpy()          # scalar (misaligned) path
-    P.pwl_set_locate(P.LOCATE_SEARCH)
-    try:
+    with locate_mode(P, P.LOCATE_MAP):
+        y = P.pwl_eval(t, x).cpu().numpy()
+        y_odd = P.pwl_eval(t, x[1:5001]).cpu().numpy()      # scalar (misaligned) path
+    with locate_mode(P, P.LOCATE_SEARCH):
         y_bs = P.pwl_eval(t, x).cpu().numpy()
-    finally:
-        P.pwl_set_locate(P.LOCATE_MAP)
     assert np.array_equal(y, y_bs, equal_nan=True)
     assert np.array_equal(y[1:5001], y_odd, equal_nan=True)
     # segments: the index map's, and the oracle's on the FP32 knots

@@ -135,3 +135,117 @@ def test_convergence_order_two(func, p, a, b, const):
                  for N in Ns]
             slopes = np.diff(np.log(e)) / np.diff(np.log(Ns))
             assert np.all(np.abs(slopes + order) <= 0.05), (part, val, slopes)
+
+
+# ---------------------------------------------------------------------------
+# Exact pins of linf_error and result1_bound (closed forms for polynomials).
+# ---------------------------------------------------------------------------
+
+def _random_partition(a, b, N, seed):
+    rng = np.random.default_rng(seed)
+    inner = np.sort(rng.uniform(a, b, N - 1))
+    return np.concatenate([[a], inner, [b]])
+
+
+def test_linf_interpolant_of_quadratic_is_max_h2_over_8():
+    # f = c x^2 / 2 has f'' = c; on [x_i, x_{i+1}] the interpolation error is
+    # (c/2)(x - x_i)(x_{i+1} - x), largest at the midpoint: c h_i^2 / 8
+    # (the interpolation remainder, Appendix A).
+    c = 2.6
+    X = _random_partition(-3.0, 5.0, 23, 11)
+    p = (0.4, -1.1, c / 2.0)
+    v = O.interp_values(O.POLY, p, X)
+    exact = c * np.max(np.diff(X)) ** 2 / 8.0
+    assert math.isclose(O.linf_error(O.POLY, p, X, v), exact, rel_tol=1e-12)
+
+
+def test_linf_uniform_projection_of_quadratic_is_h2_over_12():
+    # On a uniform partition the projection of c x^2/2 is the interpolant
+    # lowered by c h^2 / 12 on every segment (the per-segment minimiser of
+    # Appendix B, continuous because every h is equal): the error is c h^2/12
+    # at the knots and -c h^2/24 at the midpoints, so the maximum is c h^2/12.
+    # N = 32 on [-2, 6]: h = 1/4, so the FP32 knots are exactly uniform.
+    c, N = 3.0, 32
+    X, _ = O.uniform_knots(-2.0, 6.0, N)
+    h = 8.0 / N
+    assert np.all(np.diff(X) == h)
+    p = (0.0, 0.7, c / 2.0)
+    cv = O.proj_values(O.POLY, p, X)
+    assert math.isclose(O.linf_error(O.POLY, p, X, cv), c * h * h / 12.0, rel_tol=1e-10)
+
+
+def _cubic_interp_linf_exact(p, X):
+    """max |f - pi f| for f = c0 + c1 x + c2 x^2 + c3 x^3, in closed form: on
+    a segment, with u = x - x_i and h = x_{i+1} - x_i, the error is
+    e(u) = u (u - h) (A + c3 u), A = c2 + c3 (2 x_i + x_{i+1}) (the second
+    divided difference of a cubic); its extrema solve the quadratic e'(u) = 0."""
+    c2, c3 = p[2], p[3]
+    best = 0.0
+    for x0, x1 in zip(X[:-1], X[1:]):
+        h = x1 - x0
+        A = c2 + c3 * (2.0 * x0 + x1)
+        B = c3
+        qa, qb, qc = 3.0 * B, 2.0 * (A - B * h), -A * h
+        roots = [-qc / qb] if qa == 0.0 else []
+        if qa != 0.0:
+            disc = qb * qb - 4.0 * qa * qc
+            if disc >= 0.0:
+                r = math.sqrt(disc)
+                roots = [(-qb - r) / (2.0 * qa), (-qb + r) / (2.0 * qa)]
+        for u in roots:
+            if 0.0 <= u <= h:
+                best = max(best, abs(u * (u - h) * (A + B * u)))
+    return best
+
+
+def test_linf_interpolant_of_cubic_between_samples():
+    # The maximum of a cubic's interpolation error does not sit on the 33
+    # sample points of a segment, so this pins the golden-section refinement
+    # as well as the sampling.
+    p = (0.3, -0.2, 0.45, -0.37)
+    X = _random_partition(-2.5, 3.0, 17, 5)
+    v = O.interp_values(O.POLY, p, X)
+    exact = _cubic_interp_linf_exact(p, X)
+    got = O.linf_error(O.POLY, p, X, v)
+    assert math.isclose(got, exact, rel_tol=1e-10)
+    # the samples alone fall measurably short of it
+    s = np.linspace(0.0, 1.0, 33)
+    h = np.diff(X)
+    xs = X[:-1, None] + h[:, None] * s[None, :]
+    line = v[:-1, None] * (1.0 - s[None, :]) + v[1:, None] * s[None, :]
+    sampled = float(np.max(np.abs(O.f_value(O.POLY, p, xs) - line)))
+    assert sampled < exact * (1.0 - 1e-6)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_result1_bound_equals_error_for_quadratics(seed):
+    # Result 1 (Sec. III-A) is an equality when f'' is constant: the bound
+    # sqrt(sum_i max|f''|^2 h_i^5 / 120) is then the interpolant's L2 error.
+    rng = np.random.default_rng(seed)
+    p = tuple(rng.uniform(-2.0, 2.0, 3))
+    X = _random_partition(-1.0, 4.0, 29, 20 + seed)
+    err = O.l2_error(O.POLY, p, X, O.interp_values(O.POLY, p, X))
+    assert math.isclose(O.result1_bound(O.POLY, p, X), err, rel_tol=1e-12)
+
+
+def test_result1_bound_and_l2_error_of_cubic_in_closed_form():
+    # For a cubic, f'' is linear, so its maximum on a segment is at an end:
+    # the bound is sqrt(sum_i max(|f''(x_i)|, |f''(x_{i+1})|)^2 h_i^5 / 120).
+    # The squared L2 error is the exact integral of the polynomial e(u)^2.
+    p = (0.1, 0.5, -0.8, 0.6)
+    X = _random_partition(-2.0, 2.0, 13, 9)
+    f2 = lambda x: 2.0 * p[2] + 6.0 * p[3] * x
+    h = np.diff(X)
+    m = np.maximum(np.abs(f2(X[:-1])), np.abs(f2(X[1:])))
+    assert math.isclose(O.result1_bound(O.POLY, p, X), math.sqrt(float(np.sum(m * m * h ** 5 / 120.0))),
+                        rel_tol=1e-12)
+    from numpy.polynomial import polynomial as Pn
+    total = 0.0
+    for x0, x1 in zip(X[:-1], X[1:]):
+        hh = x1 - x0
+        A = p[2] + p[3] * (2.0 * x0 + x1)
+        e = Pn.polymul(Pn.polymul([0.0, 1.0], [-hh, 1.0]), [A, p[3]])   # u (u - h) (A + c3 u)
+        sq = Pn.polyint(Pn.polymul(e, e))
+        total += Pn.polyval(hh, sq) - Pn.polyval(0.0, sq)
+    v = O.interp_values(O.POLY, p, X)
+    assert math.isclose(O.l2_error(O.POLY, p, X, v) ** 2, total, rel_tol=1e-11)
