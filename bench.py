@@ -45,12 +45,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1510_02975_amd.timing import WARM_SECONDS, launch_durations, timed_median, warm_up  # noqa: E402
+
 METRIC = "Gpoints/s fwd and fwd+bwd, % HBM roofline, max err vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
 FWD_BYTES_PER_POINT = 8      # x in, y out (FP32)
 FUSED_BYTES_PER_POINT = 16   # x, g in; y, dx out
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_eval_fwd_gauss_n1024.json")
-WARM_SECONDS = 0.25          # sustained load before each timed phase
 CPU_THREADS_MAX = 16         # the GPU machine's CPU share for one GPU
 KERNEL_SOURCES = ["paper_1510_02975_amd/csrc/pwl_eval.hip", "paper_1510_02975_amd/csrc/pwl_stream.h",
                   "paper_1510_02975_amd/csrc/pwl_locate.h", "paper_1510_02975_amd/csrc/pwl_internal.h"]
@@ -85,84 +86,6 @@ def measured_traffic():
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
-
-
-class Marks:
-    """Timing-only HIP events on the current stream, created with
-    hipEventDisableSystemFence: recording one takes no system-scope fence, so
-    it neither writes back nor invalidates the caches between the kernels it
-    separates (a default event does both).  The HIP runtime is the one torch
-    loaded (same soname), so torch's stream handles are valid here."""
-    DISABLE_SYSTEM_FENCE = 0x20000000
-
-    def __init__(self, torch, count):
-        import ctypes
-        self.ctypes = ctypes
-        self.torch = torch
-        self.hip = ctypes.CDLL("libamdhip64.so.7")
-        self.hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
-        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
-        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
-        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
-        self.ev = []
-        for _ in range(count):
-            e = ctypes.c_void_p()
-            self._check(self.hip.hipEventCreateWithFlags(ctypes.byref(e), self.DISABLE_SYSTEM_FENCE))
-            self.ev.append(e)
-
-    def _check(self, rc):
-        if rc != 0:
-            raise RuntimeError("HIP event call failed with status %d" % rc)
-
-    def record(self, i, stream=None):
-        s = stream if stream is not None else self.torch.cuda.current_stream()
-        self._check(self.hip.hipEventRecord(self.ev[i], s.cuda_stream))
-
-    def ms(self, i, j):
-        out = self.ctypes.c_float()
-        self._check(self.hip.hipEventElapsedTime(self.ctypes.byref(out), self.ev[i], self.ev[j]))
-        return out.value
-
-    def free(self):
-        for e in self.ev:
-            self.hip.hipEventDestroy(e)
-        self.ev = []
-
-
-def warm_up(torch, fn, seconds=WARM_SECONDS, min_calls=0):
-    """Run fn(i) until `seconds` of sustained load have passed (and at least
-    min_calls calls); returns the seconds spent.  The GPU raises its clocks
-    under sustained load: a short warm-up times the ramp, not the kernel."""
-    t0 = time.perf_counter()
-    i = 0
-    while i < min_calls or time.perf_counter() - t0 < seconds:
-        fn(i)
-        i += 1
-        if i % 8 == 0:
-            torch.cuda.synchronize()
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
-
-
-def launch_durations(torch, fn, reps=20, warm_seconds=WARM_SECONDS):
-    """Durations (s) of `reps` back-to-back launches fn(0..reps-1) on the
-    current stream, each between two fence-free events, after warm_seconds
-    of sustained load."""
-    warm_up(torch, fn, warm_seconds)
-    m = Marks(torch, reps + 1)
-    for i in range(reps):
-        m.record(i)
-        fn(i)
-    m.record(reps)
-    torch.cuda.synchronize()
-    d = np.array([m.ms(i, i + 1) for i in range(reps)]) * 1e-3
-    m.free()
-    return d
-
-
-def timed_median(torch, fn, reps=20, warm_seconds=WARM_SECONDS):
-    """Median duration of back-to-back launches (see launch_durations)."""
-    return float(np.median(launch_durations(torch, fn, reps, warm_seconds)))
 
 
 def host_description():

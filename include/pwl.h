@@ -237,10 +237,12 @@ pwl_status pwl_eval(const pwl_table* t, const float* v_override, const float* x,
  * order, so dv is deterministic for a given launch shape).  At least one of
  * y, dx, dv must be non-NULL.  This is the exact derivative of Algorithm 1
  * (the paper gives none): dy/dx is the segment slope, dy/dv_k the hat weight.
- * Workspace: (workgroups x (N+1)) floats owned by the table, allocated by
- * the first call with dv that needs more (that call synchronises the
- * device; freed with the table).  Calls with dv on one table share it, so
- * they must not overlap in time: issue them on one stream.
+ * Workspace: (workgroups x (N+1)) floats owned by the table, taken from
+ * the stream-ordered allocator (hipMallocAsync on `stream`) by the first
+ * call with dv that needs more; the old rows are released on `stream` after
+ * their last user has finished, and the rows are freed with the table.
+ * Calls with dv on one table share them, so they must not overlap in time:
+ * issue them on one stream.
  */
 pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const float* x,
                              const float* g, float* y, float* dx, float* dv, int64_t n, void* stream);
@@ -396,6 +398,21 @@ pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32
  */
 pwl_status pwl_set_locate(int32_t mode);
 int32_t pwl_get_locate(void);
+
+#define PWL_RECORDS_PACKED 0  /* one 16-byte record {x_k, v_k, slope_k, x_{k+1}} per segment (default) */
+#define PWL_RECORDS_SOA 1     /* the same fields as four arrays of N floats                        */
+
+/*
+ * pwl_set_records - process-wide arrangement of the per-segment data that
+ * pwl_eval stages in LDS (Sec. V discusses arranging the table for the
+ * GPU's memory): packed records, where a point's lookup is one 12-byte LDS
+ * read, or structure-of-arrays, where it is three 4-byte reads.  The values
+ * are the same, so outputs are bit-identical; the choice is a speed A/B.
+ * The fused backward, the batched kernels and pwl_kde always use packed
+ * records.  Takes effect for later launches; pwl_get_records reads it back.
+ */
+pwl_status pwl_set_records(int32_t layout);
+int32_t pwl_get_records(void);
 
 /* ---- library ------------------------------------------------------------ */
 

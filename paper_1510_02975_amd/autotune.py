@@ -1,11 +1,16 @@
-"""Launch-shape autotuner for the streaming evaluation kernels.
+"""Autotuner for the streaming evaluation kernels.
 
-Times every candidate (unroll, block, workgroups per CU) of a kernel family
-on the caller's own table and points with HIP events on the current stream,
-keeps the fastest, and installs it with pwl_set_launch.  Results can be saved
-to and loaded from a JSON file keyed by kernel family.
+Axes: the launch shape (unroll, block, workgroups per CU) of every kernel
+family, and for the forward the segment locate (index map, or the paper's
+branch-free binary search over the knots, Sec. IV-V) and the arrangement of
+the per-segment data in LDS (packed records or structure of arrays, Sec. V).
+Every candidate is timed on the caller's own table and points with
+fence-free HIP events on the current stream, after a time-based warm-up;
+the fastest is installed.  save() writes the choices in the format the
+binding applies when it loads the library (tuned_mi355x.json beside this
+file), so the shipped configuration is the tuner's.
 
-    python -m paper_1510_02975_amd.autotune [--log2n 28] [--bwd-log2n 26] [--batch]
+    python -m paper_1510_02975_amd.autotune [--log2n 28] [--bwd-log2n 26] [--batch] [--out FILE]
 """
 
 import argparse
@@ -13,28 +18,22 @@ import itertools
 import json
 import os
 
-import numpy as np
 import torch
 
 from . import binding as B
+from .timing import timed_median, warm_up
 
 DEFAULT_CANDIDATES = {
     "unroll": (1, 2, 4),
     "block": (256, 512, 768, 1024),
     "wg_per_cu": (1, 2, 4, 8, 16, 24),
 }
+LOCATE_NAMES = {B.LOCATE_MAP: "map", B.LOCATE_SEARCH: "search"}
+RECORDS_NAMES = {B.RECORDS_PACKED: "packed", B.RECORDS_SOA: "soa"}
 
 
-def _time(fn, reps, warm=2):
-    for i in range(warm):
-        fn(i)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for i, (s, e) in enumerate(ev):
-        s.record()
-        fn(i)
-        e.record()
-    torch.cuda.synchronize()
-    return float(np.median([s.elapsed_time(e) for s, e in ev])) * 1e-3
+def _time(fn, reps, warm_seconds=0.05):
+    return timed_median(torch, fn, reps=reps, warm_seconds=warm_seconds)
 
 
 def tune(kernel, run, candidates=None, reps=10, verbose=False):
@@ -43,6 +42,7 @@ def tune(kernel, run, candidates=None, reps=10, verbose=False):
     cand = dict(DEFAULT_CANDIDATES)
     cand.update(candidates or {})
     results = []
+    warm_up(torch, run)
     for u, blk, w in itertools.product(cand["unroll"], cand["block"], cand["wg_per_cu"]):
         B.pwl_set_launch(kernel, u, blk, w)
         t = _time(run, reps)
@@ -84,22 +84,43 @@ def tune_batch(tables, offsets, x, y, g=None, dx=None, dv=None, candidates=None,
     return out
 
 
-def save(path, configs):
+def tune_layout(run, reps=10, verbose=False):
+    """The forward's layout A/B at its current launch shape: every
+    (locate, records) pair, timed by run(i); installs and returns the best
+    pair, its seconds and all results {(locate, records): seconds}."""
+    warm_up(torch, run)
+    res = {}
+    for loc, rec in itertools.product((B.LOCATE_MAP, B.LOCATE_SEARCH), (B.RECORDS_PACKED, B.RECORDS_SOA)):
+        B.pwl_set_locate(loc)
+        B.pwl_set_records(rec)
+        res[loc, rec] = _time(run, reps)
+        if verbose:
+            print("  forward locate %-6s records %-6s: %.1f us"
+                  % (LOCATE_NAMES[loc], RECORDS_NAMES[rec], res[loc, rec] * 1e6), flush=True)
+    best = min(res, key=res.get)
+    B.pwl_set_locate(best[0])
+    B.pwl_set_records(best[1])
+    return best, res[best], res
+
+
+def save(path, launch, locate=None, records=None, source=None, timings=None):
+    """Write the tuned choices: launch {kernel family: (unroll, block,
+    wg_per_cu)}, the forward's locate mode and record layout."""
+    rec = {"source": source or "paper_1510_02975_amd.autotune",
+           "launch": {str(k): list(v) for k, v in launch.items()}}
+    if locate is not None:
+        rec["locate"] = int(locate)
+    if records is not None:
+        rec["records"] = int(records)
+    if timings:
+        rec["timings_us"] = timings
     with open(path, "w") as fh:
-        json.dump({str(k): list(v) for k, v in configs.items()}, fh, indent=1)
+        json.dump(rec, fh, indent=1)
 
 
 def load(path):
-    """Install the configs saved by save(); missing file is a no-op."""
-    if not os.path.exists(path):
-        return {}
-    with open(path) as fh:
-        raw = json.load(fh)
-    out = {}
-    for k, v in raw.items():
-        B.pwl_set_launch(int(k), *v)
-        out[int(k)] = tuple(v)
-    return out
+    """Install the choices saved by save(); a missing file is a no-op."""
+    return B.apply_tuned(path)
 
 
 def main():
@@ -122,9 +143,19 @@ def main():
     xs = [torch.from_numpy(xh).to(dev) for _ in range(3)]
     del xh
     ys = [torch.empty(n, device=dev) for _ in range(3)]
-    best_f, tf, _ = tune(B.KERNEL_FORWARD, lambda i: B.pwl_eval(t, xs[i % 3], ys[i % 3]), verbose=True)
+    fwd = lambda i: B.pwl_eval(t, xs[i % 3], ys[i % 3])
+    B.pwl_set_locate(B.LOCATE_MAP)
+    B.pwl_set_records(B.RECORDS_PACKED)
+    best_f, tf, _ = tune(B.KERNEL_FORWARD, fwd, verbose=True)
     print("forward best", best_f, "%.1f GB/s" % (8.0 * n / tf / 1e9), flush=True)
     best[B.KERNEL_FORWARD] = best_f
+    (loc, rec), tl, lres = tune_layout(fwd, verbose=True)
+    print("forward layout A/B at %s (locate x records, us):" % (best_f,), flush=True)
+    for (lo, rc), sec in sorted(lres.items()):
+        print("  %-6s %-6s %8.1f us  %6.1f Gpoints/s" % (LOCATE_NAMES[lo], RECORDS_NAMES[rc], sec * 1e6, n / sec / 1e9),
+              flush=True)
+    print("forward layout best: locate %s, records %s" % (LOCATE_NAMES[loc], RECORDS_NAMES[rec]), flush=True)
+    timings = {"forward_%s_%s" % (LOCATE_NAMES[lo], RECORDS_NAMES[rc]): sec * 1e6 for (lo, rc), sec in lres.items()}
     del xs, ys
     # fused backward: the gradient workload (x, g ~ N(0, 1))
     gs = W.GRAD
@@ -161,7 +192,9 @@ def main():
                   flush=True)
             best[kernel] = shape
     if args.out:
-        save(args.out, best)
+        save(args.out, best, locate=loc, records=rec, timings=timings,
+             source="paper_1510_02975_amd.autotune --log2n %d --bwd-log2n %d%s on MI355X"
+                    % (args.log2n, args.bwd_log2n, " --batch" if args.batch else ""))
 
 
 if __name__ == "__main__":

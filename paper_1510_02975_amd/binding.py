@@ -79,6 +79,8 @@ _SIGNATURES = {
     "pwl_get_launch": (_c_int32, [_c_int32, _ip, _ip, _ip]),
     "pwl_set_locate": (_c_int32, [_c_int32]),
     "pwl_get_locate": (_c_int32, []),
+    "pwl_set_records": (_c_int32, [_c_int32]),
+    "pwl_get_records": (_c_int32, []),
     "pwl_last_error": (ctypes.c_char_p, []),
     "pwl_abi_version": (_c_int32, []),
 }
@@ -454,6 +456,7 @@ def pwl_get_launch(kernel):
 
 
 LOCATE_MAP, LOCATE_SEARCH = 0, 1
+RECORDS_PACKED, RECORDS_SOA = 0, 1
 KDE_TABLE, KDE_EXPF, KDE_FAST_EXPF = 0, 1, 2
 
 
@@ -492,6 +495,14 @@ def pwl_set_locate(mode):
 
 def pwl_get_locate():
     return int(load_library().pwl_get_locate())
+
+
+def pwl_set_records(layout):
+    _check(load_library().pwl_set_records(int(layout)))
+
+
+def pwl_get_records():
+    return int(load_library().pwl_get_records())
 
 
 def pwl_last_error():

@@ -999,6 +999,13 @@ pwl_status pwl_set_locate(int32_t mode) {
 
 int32_t pwl_get_locate(void) { return pwl::get_locate(); }
 
+pwl_status pwl_set_records(int32_t layout) {
+  if (pwl::set_records(layout) != hipSuccess) return fail(PWL_EINVAL, "unknown record layout %d", layout);
+  return PWL_OK;
+}
+
+int32_t pwl_get_records(void) { return pwl::get_records(); }
+
 pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32_t* wg_per_cu) {
   if (kernel < 0 || kernel > 3) return fail(PWL_EINVAL, "unknown kernel family %d", kernel);
   const pwl::LaunchConfig c = pwl::get_launch(kernel);

@@ -41,14 +41,9 @@ using namespace stream;
     __VA_ARGS__;                                                                            \
   }
 
-template <int U>
-__global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __restrict__ vo,
-                                                   const float* __restrict__ x,
-                                                   float* __restrict__ y, int64_t n, int flags) {
-  extern __shared__ float4 lds_f4[];
-  const Smem s = carve(lds_f4, t.N, t.K, false);
-  stage_table(t, vo, s);
-  __syncthreads();
+template <int U, class S>
+__device__ __forceinline__ void eval_fwd_body(const EvalTable& t, const S& s, const float* __restrict__ x,
+                                              float* __restrict__ y, int64_t n, int flags) {
   const int64_t blk = blockIdx.x, nblk = gridDim.x;
   const bool vec = (flags & 1) != 0;
   if (flags & 2) {   // PWL_LOCATE_SEARCH
@@ -62,6 +57,26 @@ __global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __r
     case 3: fwd_range<U, 3>(t, s, x, y, 0, n, vec, blk, nblk); break;
     case 4: fwd_range<U, 4>(t, s, x, y, 0, n, vec, blk, nblk); break;
     default: fwd_range<U, 0>(t, s, x, y, 0, n, vec, blk, nblk); break;
+  }
+}
+
+// SOA selects the structure-of-arrays records (PWL_RECORDS_SOA) instead of
+// the packed ones.
+template <int U, bool SOA>
+__global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __restrict__ vo,
+                                                   const float* __restrict__ x,
+                                                   float* __restrict__ y, int64_t n, int flags) {
+  extern __shared__ float4 lds_f4[];
+  if constexpr (SOA) {
+    const SmemSoA s = carve_soa(lds_f4, t.N, t.K);
+    stage_table(t, vo, s);
+    __syncthreads();
+    eval_fwd_body<U>(t, s, x, y, n, flags);
+  } else {
+    const Smem s = carve(lds_f4, t.N, t.K, false);
+    stage_table(t, vo, s);
+    __syncthreads();
+    eval_fwd_body<U>(t, s, x, y, n, flags);
   }
 }
 
@@ -290,6 +305,7 @@ inline bool same_phase(const void* a, const void* b) {
 constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 16}, {1, 1024, 16}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
+int g_records = PWL_RECORDS_PACKED;
 
 LaunchShape stream_shape(const LaunchConfig& c, size_t lds, int64_t n4, int64_t n, int num_cu) {
   const int block = c.block;
@@ -327,17 +343,38 @@ hipError_t set_locate(int mode) {
 
 int get_locate() { return g_locate; }
 
+hipError_t set_records(int layout) {
+  if (layout != PWL_RECORDS_PACKED && layout != PWL_RECORDS_SOA) return hipErrorInvalidValue;
+  g_records = layout;
+  return hipSuccess;
+}
+
+int get_records() { return g_records; }
+
 hipError_t launch_eval(const EvalTable& t, const float* vo, const float* x, float* y, int64_t n,
                        int num_cu, hipStream_t s) {
   const bool vec = same_phase(x, y) && (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const LaunchConfig c = g_launch[0];
-  const LaunchShape ls = stream_shape(c, eval_lds_bytes(t.N, t.K, false), vec ? n / 4 : 0, n, num_cu);
+  const bool soa = g_records == PWL_RECORDS_SOA;
+  const size_t lds = soa ? eval_lds_bytes_soa(t.N, t.K) : eval_lds_bytes(t.N, t.K, false);
+  const LaunchShape ls = stream_shape(c, lds, vec ? n / 4 : 0, n, num_cu);
   const int v = (vec ? 1 : 0) | (g_locate == PWL_LOCATE_SEARCH ? 2 : 0);
-  switch (c.unroll) {
-    case 1: hipLaunchKernelGGL(k_eval_fwd<1>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
-    case 2: hipLaunchKernelGGL(k_eval_fwd<2>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
-    default: hipLaunchKernelGGL(k_eval_fwd<4>, dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v); break;
+#define PWL_FWD(UU, SS) \
+  hipLaunchKernelGGL((k_eval_fwd<UU, SS>), dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v)
+  if (soa) {
+    switch (c.unroll) {
+      case 1: PWL_FWD(1, true); break;
+      case 2: PWL_FWD(2, true); break;
+      default: PWL_FWD(4, true); break;
+    }
+  } else {
+    switch (c.unroll) {
+      case 1: PWL_FWD(1, false); break;
+      case 2: PWL_FWD(2, false); break;
+      default: PWL_FWD(4, false); break;
+    }
   }
+#undef PWL_FWD
   return hipGetLastError();
 }
 
@@ -457,9 +494,12 @@ hipError_t configure_eval_kernels(int max_lds) {
   e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, lim);    \
   if (e != hipSuccess) return e;
   PWL_ATTR(k_locate)
-  PWL_ATTR(k_eval_fwd<1>)
-  PWL_ATTR(k_eval_fwd<2>)
-  PWL_ATTR(k_eval_fwd<4>)
+  PWL_ATTR((k_eval_fwd<1, false>))
+  PWL_ATTR((k_eval_fwd<2, false>))
+  PWL_ATTR((k_eval_fwd<4, false>))
+  PWL_ATTR((k_eval_fwd<1, true>))
+  PWL_ATTR((k_eval_fwd<2, true>))
+  PWL_ATTR((k_eval_fwd<4, true>))
 #define PWL_ATTR_U(U)                            \
   PWL_ATTR((k_eval_bwd<U, false, false, true>))  \
   PWL_ATTR((k_eval_bwd<U, false, true, false>))  \

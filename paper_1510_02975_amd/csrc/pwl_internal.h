@@ -75,6 +75,12 @@ struct BuildParams {
 __host__ __device__ inline int image_knot_words(int N) { return (N + kKnotPad + 3) / 4; }
 __host__ __device__ inline int image_map_words(int K) { return (K + 1 + 7) / 8; }
 __host__ __device__ inline int image_words(int N, int K) { return N + image_knot_words(N) + image_map_words(K); }
+// The structure-of-arrays variant (forward only): each of the four record
+// fields is an array of N floats rounded up to whole words.
+__host__ __device__ inline int image_soa_field_words(int N) { return (N + 3) / 4; }
+__host__ __device__ inline int image_words_soa(int N, int K) {
+  return 4 * image_soa_field_words(N) + image_knot_words(N) + image_map_words(K);
+}
 
 // LDS bytes of the evaluation kernels for a table of N segments and K cells:
 // the image, then (backward) the workgroup's FP64 dL/dv.
@@ -83,6 +89,8 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
   if (backward) b += sizeof(double) * (size_t)(N + 1);
   return b;
 }
+
+inline size_t eval_lds_bytes_soa(int N, int K) { return 16 * (size_t)image_words_soa(N, K); }
 
 // Table finalize: 4 FP64 PCR rows, the FP32 knots and their u16 map cells.
 inline size_t finalize_lds_bytes(int N) {
@@ -114,6 +122,8 @@ hipError_t set_launch(int kernel, int unroll, int block, int wg_per_cu);
 LaunchConfig get_launch(int kernel);
 hipError_t set_locate(int mode);
 int get_locate();
+hipError_t set_records(int layout);
+int get_records();
 
 // ---- batched evaluation ----------------------------------------------------
 // A batch copies every table's LDS image (the layout carve() describes:

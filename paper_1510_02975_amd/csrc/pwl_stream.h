@@ -14,11 +14,34 @@ namespace stream {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// Packed records: one 16-byte word per segment (a segment's lookup is one
+// LDS read of 12 or 16 bytes).
 struct Smem {
   float4* rec;      // [N]           {x_k, v_k, slope_k, x_{k+1}}
   float* knot;      // [N + pad]     knot[k] = x_k for 1 <= k <= N-1, NaN elsewhere
   uint16_t* lo;     // [K + 1]       lo[u] = #{interior knots in cells < u}; lo[K] = N - 1
   double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
+  __device__ __forceinline__ float4 record(int k) const { return rec[k]; }
+  __device__ __forceinline__ void put_record(int k, float4 r) const { rec[k] = r; }
+};
+
+// Structure-of-arrays records: the four fields of the records in four
+// arrays of N floats (a lookup reads each field it uses separately; the
+// forward's three reads are 4 bytes each).  Forward evaluation only.
+struct SmemSoA {
+  float* rx;        // [N] x_k
+  float* rv;        // [N] v_k
+  float* rs;        // [N] slope_k
+  float* rw;        // [N] x_{k+1}
+  float* knot;
+  uint16_t* lo;
+  __device__ __forceinline__ float4 record(int k) const { return make_float4(rx[k], rv[k], rs[k], rw[k]); }
+  __device__ __forceinline__ void put_record(int k, float4 r) const {
+    rx[k] = r.x;
+    rv[k] = r.y;
+    rs[k] = r.z;
+    rw[k] = r.w;
+  }
 };
 
 // Sections of a table image (see image_words).  Every pointer is an offset
@@ -31,6 +54,22 @@ __device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
   s.knot = reinterpret_cast<float*>(s.rec + N);
   s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
   s.dv = backward ? reinterpret_cast<double*>(reinterpret_cast<float4*>(s.lo) + image_map_words(K)) : nullptr;
+  return s;
+}
+
+// The structure-of-arrays image: four record arrays of image_soa_field_words
+// words each, then the knots and the map as in carve.
+__device__ __forceinline__ SmemSoA carve_soa(void* base, int N, int K) {
+  SmemSoA s;
+  const int fw = image_soa_field_words(N);
+  float4* b4 = reinterpret_cast<float4*>(base);
+  s.rx = reinterpret_cast<float*>(b4);
+  s.rv = reinterpret_cast<float*>(b4 + fw);
+  s.rs = reinterpret_cast<float*>(b4 + 2 * fw);
+  s.rw = reinterpret_cast<float*>(b4 + 3 * fw);
+  s.knot = reinterpret_cast<float*>(b4 + 4 * fw);
+  s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
+  (void)K;
   return s;
 }
 
@@ -80,7 +119,8 @@ __device__ __forceinline__ float4 map_word(const EvalTable& t, int w) {
 // workgroup), each thread loads its words before it writes any, so the copy
 // waits on one round of loads instead of one per section; the straight-line
 // form keeps the kernels' register use where the streaming loop needs it.
-__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo, const Smem& s) {
+template <class S>
+__device__ __forceinline__ void stage_table(const EvalTable& t, const float* __restrict__ vo, const S& s) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nkw = image_knot_words(t.N), nmw = image_map_words(t.K);
   float4* knot4 = reinterpret_cast<float4*>(s.knot);
@@ -91,12 +131,12 @@ __device__ __forceinline__ void stage_table(const EvalTable& t, const float* __r
     if (hr) r = record_word(t, vo, tid);
     if (hk) k = knot_word(t, tid);
     if (hm) m = map_word(t, tid);
-    if (hr) s.rec[tid] = r;
+    if (hr) s.put_record(tid, r);
     if (hk) knot4[tid] = k;
     if (hm) map4[tid] = m;
     return;
   }
-  for (int w = tid; w < t.N; w += nt) s.rec[w] = record_word(t, vo, w);
+  for (int w = tid; w < t.N; w += nt) s.put_record(w, record_word(t, vo, w));
   for (int w = tid; w < nkw; w += nt) knot4[w] = knot_word(t, w);
   for (int w = tid; w < nmw; w += nt) map4[w] = map_word(t, w);
 }
@@ -109,8 +149,8 @@ __device__ __forceinline__ float clamp_nan(float x, float a, float b) {
 // the MAXC knots that follow lo[cell(x)].  Knots beyond the cell's own are
 // greater than x (they lie in later cells) and the sentinels are NaN, so the
 // extra compares are false; the count of true compares is exact.
-template <int MAXC>
-__device__ __forceinline__ int locate_fixed(float x, const EvalTable& t, const Smem& s) {
+template <int MAXC, class S>
+__device__ __forceinline__ int locate_fixed(float x, const EvalTable& t, const S& s) {
   const int u = map_cell(x, t.a32, t.scale32, t.K);
   const int lo = s.lo[u];
   int seg = lo;
@@ -120,7 +160,8 @@ __device__ __forceinline__ int locate_fixed(float x, const EvalTable& t, const S
 }
 
 // Any number of knots per cell: the count is lo[u+1] - lo[u].
-__device__ __forceinline__ int locate_any(float x, const EvalTable& t, const Smem& s) {
+template <class S>
+__device__ __forceinline__ int locate_any(float x, const EvalTable& t, const S& s) {
   const int u = map_cell(x, t.a32, t.scale32, t.K);
   const int lo = s.lo[u];
   const int cnt = (int)s.lo[u + 1] - lo;
@@ -133,7 +174,8 @@ __device__ __forceinline__ int locate_any(float x, const EvalTable& t, const Sme
 // knots, here the interior knots in LDS.  It counts the interior knots <= x
 // (so x_i <= x < x_{i+1}; NaN x compares false and gives 0), halving a
 // power-of-two step from the largest one below N.
-__device__ __forceinline__ int locate_search(float x, const EvalTable& t, const Smem& s) {
+template <class S>
+__device__ __forceinline__ int locate_search(float x, const EvalTable& t, const S& s) {
   int lo = 0;
   for (int half = (t.N > 1) ? (1 << (31 - __builtin_clz(t.N - 1))) : 0; half >= 1; half >>= 1) {
     const int k = lo + half;
@@ -144,17 +186,17 @@ __device__ __forceinline__ int locate_search(float x, const EvalTable& t, const 
 
 // MAXC > 0: map + MAXC unrolled compares; 0: map + counted compares;
 // -1: binary search without the map.
-template <int MAXC>
-__device__ __forceinline__ int locate(float x, const EvalTable& t, const Smem& s) {
+template <int MAXC, class S>
+__device__ __forceinline__ int locate(float x, const EvalTable& t, const S& s) {
   if (MAXC > 0) return locate_fixed<MAXC>(x, t, s);
   if (MAXC < 0) return locate_search(x, t, s);
   return locate_any(x, t, s);
 }
 
-template <int MAXC>
-__device__ __forceinline__ float eval_point(float x, const EvalTable& t, const Smem& s) {
+template <int MAXC, class S>
+__device__ __forceinline__ float eval_point(float x, const EvalTable& t, const S& s) {
   const int seg = locate<MAXC>(x, t, s);
-  const float4 r = s.rec[seg];
+  const float4 r = s.record(seg);
   return fmaf(clamp_nan(x, t.a32, t.b32) - r.x, r.z, r.y);
 }
 
@@ -193,8 +235,8 @@ __device__ __forceinline__ void backward_point(float x, float g, const EvalTable
 // can count outstanding memory operations exactly (a guarded load makes
 // every later wait a wait for all stores); the last, partial iteration of a
 // thread is guarded.
-template <int U, int MAXC, bool GUARD>
-__device__ __forceinline__ void fwd_iter(const EvalTable& t, const Smem& s, const v4f* __restrict__ x4,
+template <int U, int MAXC, bool GUARD, class S>
+__device__ __forceinline__ void fwd_iter(const EvalTable& t, const S& s, const v4f* __restrict__ x4,
                                          v4f* __restrict__ y4, int64_t base, int64_t bs, int64_t n4) {
   v4f xv[U];
 #pragma unroll
@@ -245,8 +287,8 @@ __device__ __forceinline__ Split split_range(const float* p, int64_t begin, int6
 // Forward over points [begin, end) by `nblk` cooperating workgroups (this one
 // is number `blk`): workgroup blk streams vectors blk*bs*U + u*bs + tid of
 // each stride of nblk*bs*U vectors.
-template <int U, int MAXC>
-__device__ __forceinline__ void fwd_range(const EvalTable& t, const Smem& s, const float* __restrict__ x,
+template <int U, int MAXC, class S>
+__device__ __forceinline__ void fwd_range(const EvalTable& t, const S& s, const float* __restrict__ x,
                                           float* __restrict__ y, int64_t begin, int64_t end, bool vec,
                                           int64_t blk, int64_t nblk) {
   const Split sp = split_range(x, begin, end, vec);

@@ -81,3 +81,18 @@ class launch_shape:
 
     def __exit__(self, *exc):
         self.P.pwl_set_launch(self.kernel, *self.prev)
+
+
+class records_layout:
+    """Run a block with pwl_set_records(layout), then restore the layout in
+    force before."""
+
+    def __init__(self, P, layout):
+        self.P, self.layout = P, layout
+
+    def __enter__(self):
+        self.prev = self.P.pwl_get_records()
+        self.P.pwl_set_records(self.layout)
+
+    def __exit__(self, *exc):
+        self.P.pwl_set_records(self.prev)

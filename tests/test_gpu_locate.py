@@ -3,8 +3,10 @@
 each against the FP64 oracle: both must return the oracle's segment index
 (Algorithm 1, step 1) on the GPU's own knots, exactly, and pwl_eval through
 either must match the oracle's evaluation; the two modes' outputs are then
-bit-identical.  Points: random, every knot and its FP32 neighbours, the
-domain ends, points outside, +-inf and NaN."""
+bit-identical.  The same for the two arrangements of the per-segment data
+in LDS (packed records and structure of arrays, Sec. V), under both locate
+modes.  Points: random, every knot and its FP32 neighbours, the domain ends,
+points outside, +-inf and NaN."""
 
 import numpy as np
 import pytest
@@ -12,7 +14,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from tests.gpu_util import Y_TOL, device, fmax_abs, library, locate_mode, say
+from tests.gpu_util import Y_TOL, device, fmax_abs, library, locate_mode, records_layout, say
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +29,17 @@ TABLES = [
 ]
 
 
+def _points(t, a, b):
+    """Random points on a widened domain, every knot and its FP32
+    neighbours, the ends, +-inf, NaN and signed zeros."""
+    import paper_1510_02975_amd as P
+    X = P.pwl_table_download(t)["knots"]
+    pts = [W.uniform_points(a - 1.0, b + 1.0, 100003, 3),
+           X, np.nextafter(X, np.float32(-np.inf)), np.nextafter(X, np.float32(np.inf)),
+           np.array([a, b, -np.inf, np.inf, np.nan, 0.0, -0.0], np.float32)]
+    return np.concatenate(pts).astype(np.float32)
+
+
 @pytest.mark.parametrize("spec", TABLES)
 def test_binary_search_locate_matches_index_map(spec):
     import paper_1510_02975_amd as P
@@ -34,11 +47,7 @@ def test_binary_search_locate_matches_index_map(spec):
     dev = device()
     func, p, a, b, N, part, vals = spec
     t = P.pwl_build(func, p, a, b, N, part, vals)
-    X = P.pwl_table_download(t)["knots"]
-    pts = [W.uniform_points(a - 1.0, b + 1.0, 100003, 3),
-           X, np.nextafter(X, np.float32(-np.inf)), np.nextafter(X, np.float32(np.inf)),
-           np.array([a, b, -np.inf, np.inf, np.nan, 0.0, -0.0], np.float32)]
-    xh = np.concatenate(pts).astype(np.float32)
+    xh = _points(t, a, b)
     x = torch.from_numpy(xh).to(dev)
     with locate_mode(P, P.LOCATE_MAP):
         y_map = P.pwl_eval(t, x).cpu().numpy()
@@ -61,4 +70,42 @@ def test_binary_search_locate_matches_index_map(spec):
     assert np.max(np.abs(y_bs[fin] - y_ref[fin])) <= Y_TOL * scale
     assert np.array_equal(y_map, y_bs, equal_nan=True)
     assert np.array_equal(y_map[1:4000], y_bs_odd, equal_nan=True)
+    t.free()
+
+
+@pytest.mark.parametrize("spec", TABLES)
+def test_record_layouts_match_oracle(spec):
+    """Structure-of-arrays records against the oracle and bit-identical to
+    the packed ones, with the index map and with the binary search; also on
+    the scalar (misaligned) path and with a vertex-value override."""
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    func, p, a, b, N, part, vals = spec
+    t = P.pwl_build(func, p, a, b, N, part, vals)
+    xh = _points(t, a, b)
+    x = torch.from_numpy(xh).to(dev)
+    d = P.pwl_table_download(t)
+    Xg, vg = d["knots"].astype(np.float64), d["values"].astype(np.float64)
+    vo = torch.from_numpy((1.0 + 0.5 * np.cos(np.arange(N + 1))).astype(np.float32)).to(dev)
+    out = {}
+    for rec in (P.RECORDS_PACKED, P.RECORDS_SOA):
+        for mode in (P.LOCATE_MAP, P.LOCATE_SEARCH):
+            with records_layout(P, rec), locate_mode(P, mode):
+                out[rec, mode] = (P.pwl_eval(t, x).cpu().numpy(), P.pwl_eval(t, x[1:4000]).cpu().numpy(),
+                                  P.pwl_eval(t, x, v_override=vo).cpu().numpy())
+    say("  f=%d N=%d: %d points, 4 variants" % (func, N, x.numel()))
+    fin = ~np.isnan(xh)
+    y_ref = O.evaluate(Xg, vg, xh.astype(np.float64))
+    scale = fmax_abs(func, p, a, b)
+    y_soa = out[P.RECORDS_SOA, P.LOCATE_MAP][0]
+    assert np.array_equal(np.isnan(y_soa), np.isnan(y_ref))
+    assert np.max(np.abs(y_soa[fin] - y_ref[fin])) <= Y_TOL * scale
+    y_vo_ref = O.evaluate(Xg, vo.cpu().numpy().astype(np.float64), xh.astype(np.float64))
+    y_vo = out[P.RECORDS_SOA, P.LOCATE_MAP][2]
+    assert np.max(np.abs(y_vo[fin] - y_vo_ref[fin])) <= 4e-6 * 1.5
+    base = out[P.RECORDS_PACKED, P.LOCATE_MAP]
+    for key, val in out.items():
+        for a_, b_ in zip(base, val):
+            assert np.array_equal(a_, b_, equal_nan=True), key
     t.free()
