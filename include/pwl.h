@@ -248,6 +248,26 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
                              const float* g, float* y, float* dx, float* dv, int64_t n, void* stream);
 
 /*
+ * pwl_eval_backward_noalloc - pwl_eval_backward for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels, launch shape
+ * and results (bit-identical outputs), but the dL/dv partial sums live in a
+ * fixed device array of the library (8 MiB, 2^21 floats per device, held
+ * until the process ends) instead of a workspace of the table.  It calls no
+ * allocation routine.  Arguments are as in pwl_eval_backward.  Returns
+ * PWL_ECAPACITY, enqueuing nothing, when dv is requested and the launch
+ * needs more than 2^21 floats (workgroups x (N + 1); the default backward
+ * shape needs at most 256 x 4097 on a 256-CU device).  Every call on a
+ * device shares that device's array: calls with dv that overlap in time on
+ * one device (other streams, other threads) race and give wrong gradients,
+ * so issue them on one stream.  The table must have been built (that first
+ * library call on the device does the one-time set-up).
+ */
+pwl_status pwl_eval_backward_noalloc(const pwl_table* t, const float* v_override, const float* x,
+                                     const float* g, float* y, float* dx, float* dv, int64_t n,
+                                     void* stream);
+
+/*
  * pwl_locate - the 0-based segment index i with x_i <= x < x_{i+1} of each
  * point (step 1 of Algorithm 1), after clamping to [a, b]; x = b gives N-1,
  * NaN gives 0.  seg is device int32 [n].  It runs the very locate the

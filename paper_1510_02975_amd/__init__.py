@@ -16,7 +16,7 @@ from .binding import (  # noqa: F401
     NORM_LINF, OPTIMAL, POLY, PROJ, SAMPLED, UNIFORM, Batch, PWLError, PWLFunction, PWLTable, Table, load_library,
     pwl_abi_version, pwl_batch_capture, pwl_batch_create, pwl_batch_eval, pwl_batch_eval_backward,
     pwl_batch_free, pwl_batch_info, pwl_batch_replay, pwl_build, pwl_build_sampled, pwl_build_tol, pwl_copy,
-    pwl_direct_eval, pwl_direct_gaussian, pwl_eval, pwl_eval_backward, pwl_kde, pwl_get_launch, pwl_get_locate, pwl_last_error,
+    pwl_direct_eval, pwl_direct_gaussian, pwl_eval, pwl_eval_backward, pwl_eval_backward_noalloc, pwl_kde, pwl_get_launch, pwl_get_locate, pwl_last_error,
     pwl_locate, pwl_set_locate, pwl_set_records, pwl_get_records,
     pwl_plan_tol, pwl_rebuild, pwl_set_launch, pwl_table_check, pwl_table_download, pwl_table_free,
     pwl_table_info)

@@ -62,6 +62,7 @@ _SIGNATURES = {
     "pwl_table_free": (None, [_vp]),
     "pwl_eval": (_c_int32, [_vp, _vp, _vp, _vp, _c_int64, _vp]),
     "pwl_eval_backward": (_c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int64, _vp]),
+    "pwl_eval_backward_noalloc": (_c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c_int64, _vp]),
     "pwl_locate": (_c_int32, [_vp, _vp, _vp, _c_int64, _vp]),
     "pwl_direct_gaussian": (_c_int32, [_vp, _vp, _c_int64, ctypes.c_float, ctypes.c_float, _c_int32, _vp]),
     "pwl_copy": (_c_int32, [_vp, _vp, _c_int64, _vp]),
@@ -325,6 +326,25 @@ def pwl_eval_backward(table, x, g, y=None, dx=None, dv=None, v_override=None, st
     if dv is not None and dv.numel() != table.N + 1:
         raise ValueError("dv must have N + 1 elements")
     _check(load_library().pwl_eval_backward(
+        table.handle, _ptr(v_override, name="v_override"), _ptr(x, name="x"), _ptr(g, name="g"),
+        _ptr(y, name="y"), _ptr(dx, name="dx"), _ptr(dv, name="dv"), x.numel(), _stream(stream)))
+    return y, dx, dv
+
+
+def pwl_eval_backward_noalloc(table, x, g, y, dx, dv, v_override=None, stream=None):
+    """pwl_eval_backward with the dL/dv partial sums in the library's fixed
+    device scratch: the caller passes every output it wants (None for the
+    others) and nothing is allocated."""
+    if g.numel() != x.numel():
+        raise ValueError("g must have as many elements as x")
+    for name, a in (("y", y), ("dx", dx)):
+        if a is not None and a.numel() != x.numel():
+            raise ValueError("%s must have as many elements as x" % name)
+    if v_override is not None and v_override.numel() != table.N + 1:
+        raise ValueError("v_override must have N + 1 elements")
+    if dv is not None and dv.numel() != table.N + 1:
+        raise ValueError("dv must have N + 1 elements")
+    _check(load_library().pwl_eval_backward_noalloc(
         table.handle, _ptr(v_override, name="v_override"), _ptr(x, name="x"), _ptr(g, name="g"),
         _ptr(y, name="y"), _ptr(dx, name="dx"), _ptr(dv, name="dv"), x.numel(), _stream(stream)))
     return y, dx, dv

@@ -73,8 +73,18 @@ pwl_status fail(pwl_status s, const char* fmt, ...) {
 // ---- device properties and one-time kernel configuration -------------------
 
 constexpr int kMaxDevices = 64;
+// Device scratch of pwl_eval_backward_noalloc: the fused backward's dL/dv
+// partial sums (one row of N + 1 per workgroup), at most kScratchFloats
+// floats (8 MiB).  Every device that runs the library holds its own copy
+// until the process ends.  Host code reaches it only through the device
+// address taken once per device at set-up (g_scratch): the array's name is a
+// host-side stand-in, not a device address.
+constexpr size_t kScratchFloats = size_t(1) << 21;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
 int g_num_cu[kMaxDevices];
 int g_max_lds[kMaxDevices];
+float* g_scratch[kMaxDevices];   // this device's `scratch`
 hipStream_t g_aux[kMaxDevices];   // library-internal stream for small host reads
 std::once_flag g_cfg_once[kMaxDevices];
 hipError_t g_cfg_err[kMaxDevices];
@@ -92,6 +102,9 @@ pwl_status device_ready(int* dev_out, int* num_cu, int* max_lds = nullptr) {
     if (e == hipSuccess) e = pwl::configure_batch_kernels(lds);
     if (e == hipSuccess) e = pwl::configure_kde_kernels(lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&g_aux[dev], hipStreamNonBlocking);
+    void* sp = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    g_scratch[dev] = static_cast<float*>(sp);
     g_num_cu[dev] = cu > 0 ? cu : 1;
     g_max_lds[dev] = lds;
     g_cfg_err[dev] = e;
@@ -603,6 +616,36 @@ pwl_status pwl_eval_backward(const pwl_table* t, const float* v_override, const 
   }
   PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, t->part, n, num_cu, s));
   PWL_HIP(hipEventRecord(t->part_used, s));
+  return PWL_OK;
+}
+
+pwl_status pwl_eval_backward_noalloc(const pwl_table* t, const float* v_override, const float* x, const float* g,
+                                     float* y, float* dx, float* dv, int64_t n, void* stream) {
+  if (t == nullptr) return fail(PWL_EINVAL, "table is NULL");
+  if (n < 0) return fail(PWL_EINVAL, "n must be >= 0");
+  if (y == nullptr && dx == nullptr && dv == nullptr)
+    return fail(PWL_EINVAL, "at least one of y, dx, dv must be non-NULL");
+  if (n > 0 && (x == nullptr || g == nullptr)) return fail(PWL_EINVAL, "x and g must be non-NULL");
+  if (n == 0 && dv == nullptr) return PWL_OK;
+  int num_cu = 1, dev = 0;
+  pwl_status st = check_table(t, &num_cu);
+  if (st != PWL_OK) return st;
+  PWL_HIP(hipGetDevice(&dev));
+  const pwl::EvalTable e = eval_view(t);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* part = nullptr;
+  if (dv != nullptr && n > 0) {
+    // the same launch shape (and so the same rows) as pwl_eval_backward
+    const size_t need = pwl::backward_workspace_floats(e, x, g, y, dx, n, num_cu);
+    if (need > kScratchFloats)
+      return fail(PWL_ECAPACITY,
+                  "pwl_eval_backward_noalloc: the dL/dv partial sums need %zu floats (workgroups x (N + 1)), "
+                  "above the %zu of its fixed device scratch; use pwl_eval_backward or a smaller backward "
+                  "launch shape",
+                  need, kScratchFloats);
+    part = g_scratch[dev];
+  }
+  PWL_HIP(pwl::launch_eval_backward(e, v_override, x, g, y, dx, dv, part, n, num_cu, s));
   return PWL_OK;
 }
 
