@@ -322,6 +322,29 @@ def ingest_trace(trace_dir, out_md, command):
     print("\n".join(lines))
 
 
+def ingest_counters(pmc_dirs, out_md, command):
+    """Text summary of rocprofv3 --pmc runs (one directory per pass): per
+    kernel and counter, the median value per dispatch."""
+    per = {}
+    for d in pmc_dirs:
+        for r in _kernel_rows(_find(d, "counter_collection.csv")):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+            name = name.split("(")[0] if "(" in name else name
+            per.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for k in per.values() for c in k})
+    lines = ["# rocprofv3 counters (median per dispatch)", "", "Commands (from the repository root), one per pass:", ""]
+    lines += ["    " + c for c in command.split(" ;; ")]
+    lines += ["", "| kernel | dispatches | " + " | ".join(counters) + " |",
+              "|---|---|" + "---|" * len(counters)]
+    for name, cs in sorted(per.items(), key=lambda kv: kv[0]):
+        nd = max(len(v) for v in cs.values())
+        cells = ["%.4g" % float(np.median(cs[c])) if c in cs else "" for c in counters]
+        lines.append("| %s | %d | %s |" % (name, nd, " | ".join(cells)))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def batch_extra(torch, P, W, dev, args):
     """Many-table workload: 4096 tables of uneven N and uneven point counts
     (about 2^28 points in total), one batched launch (eager and replayed
@@ -461,6 +484,26 @@ def kde_extra(torch, P, W, dev):
     return out
 
 
+def layout_extra(torch, P, table, xs, ys, n):
+    """The forward's locate (index map, or the paper's binary search over
+    the knots, Sec. IV-V) and record layout (packed or structure of arrays,
+    Sec. V) on the headline table and points: every pair, and which one the
+    library runs."""
+    mode, rec = P.pwl_get_locate(), P.pwl_get_records()
+    out = {}
+    for lo, ln in ((P.LOCATE_MAP, "map"), (P.LOCATE_SEARCH, "search")):
+        for rc, rn in ((P.RECORDS_PACKED, "packed"), (P.RECORDS_SOA, "soa")):
+            P.pwl_set_locate(lo)
+            P.pwl_set_records(rc)
+            t = timed_median(torch, lambda i: P.pwl_eval(table, xs[i % len(xs)], ys[i % len(ys)]))
+            out["fwd_%s_%s_us" % (ln, rn)] = t * 1e6
+    P.pwl_set_locate(mode)
+    P.pwl_set_records(rec)
+    out["fwd_layout_in_use"] = "%s_%s" % ("map" if mode == P.LOCATE_MAP else "search",
+                                          "packed" if rec == P.RECORDS_PACKED else "soa")
+    return out
+
+
 def fused_extra(torch, P, W, dev):
     """Fused forward + backward on the gradient workload (N = 512 projection,
     2^26 points, x and g ~ N(0, 1)): the library's launch shape and a few
@@ -502,6 +545,10 @@ def main():
         # --ingest-pmc FETCH_DIR WRITE_DIR LOG2N "command"
         ingest_pmc(sys.argv[2], sys.argv[3], sys.argv[5], 1 << int(sys.argv[4]))
         return 0
+    if len(sys.argv) > 1 and sys.argv[1] == "--ingest-counters":
+        # --ingest-counters OUT_MD "cmd1 ;; cmd2 ..." DIR...
+        ingest_counters(sys.argv[4:], sys.argv[2], sys.argv[3])
+        return 0
     if len(sys.argv) > 1 and sys.argv[1] == "--ingest-trace":
         # --ingest-trace TRACE_DIR OUT_MD "command"
         ingest_trace(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -518,6 +565,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-unscaled", action="store_true")
     ap.add_argument("--batch-log2n", type=int, default=28)
+    ap.add_argument("--legs", default="layout,direct,fused,c3,kde,batch",
+                    help="secondary measurements to run (comma list; --no-extra runs none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -648,28 +697,30 @@ def main():
     extra["eval_vs_copy"] = float(np.mean(d_copy)) / eval_s
     extra["paper"] = paper_figures()
     xg_h = gg_h = None
-    if not args.no_extra:
-        log("extras: binary-search locate, direct expf, fused forward+backward")
-        # the paper's own locate (binary search over the knots) on the same table and points
-        mode = P.pwl_get_locate()
-        P.pwl_set_locate(P.LOCATE_SEARCH if mode == P.LOCATE_MAP else P.LOCATE_MAP)
-        t_alt = timed_median(torch, lambda i: P.pwl_eval(tables[0], xs[i % sets], ys[i % sets]))
-        P.pwl_set_locate(mode)
-        alt = "search" if mode == P.LOCATE_MAP else "map"
-        extra["locate_%s_eval_us" % alt] = t_alt * 1e6
-        extra["locate_%s_gpoints_s" % alt] = n / t_alt / 1e9
+    legs = set() if args.no_extra else set(args.legs.split(","))
+    if args.no_batch:
+        legs.discard("batch")
+    if "layout" in legs:
+        log("extras: locate and record-layout A/B")
+        extra.update(layout_extra(torch, P, tables[0], xs, ys, n))
+    if "direct" in legs:
+        log("extras: direct expf")
         for fast in (0, 1):
             t = timed_median(torch, lambda i: P.pwl_direct_gaussian(xs[i % sets], ys[i % sets], 1.0, 1.0, fast))
             extra["direct_%s_gpoints_s" % ("fast_expf" if fast else "expf")] = n / t / 1e9
+    if "fused" in legs:
+        log("extras: fused forward+backward")
         fx, xg_h, gg_h = fused_extra(torch, P, W, dev)
         extra.update(fx)
+    if "c3" in legs:
         log("extras: Lorentzian and J0 tables, 2^27 points")
         extra.update(c3_extra(torch, P, W, dev))
+    if "kde" in legs:
         log("extras: sample application (per-pixel kernel sums)")
         extra.update(kde_extra(torch, P, W, dev))
-        if not args.no_batch:
-            del xs, ys
-            extra.update(batch_extra(torch, P, W, dev, args))
+    if "batch" in legs:
+        del xs, ys
+        extra.update(batch_extra(torch, P, W, dev, args))
 
     cpu = None
     max_err = None

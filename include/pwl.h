@@ -289,13 +289,15 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
  *                new batch to be seen).
  *   offsets[T+1] HOST array, offsets[0] = 0, non-decreasing (empty tables
  *                allowed); offsets[T] is the total number of points.
- * Each direction is one launch whose grid holds the workgroups per CU of
- * the PWL_KERNEL_BATCH (forward) or PWL_KERNEL_BATCH_BACKWARD launch shape
- * current at creation; every workgroup reserves the LDS of the largest
- * table.  The points are cut into one contiguous chunk of equal cost per
- * workgroup (a table switch costs as much as 4096 points); each workgroup
- * walks the table runs of its chunk and re-stages its LDS copy of the table
- * only when the table changes.
+ * Each direction is one launch.  The points are cut into the workgroups
+ * per CU of the PWL_KERNEL_BATCH (forward) or PWL_KERNEL_BATCH_BACKWARD
+ * launch shape current at creation, one contiguous chunk of equal cost per
+ * workgroup (a table switch costs as much as 4096 points); a chunk whose
+ * tables' LDS images (and, backward, their FP64 dL/dv) do not fit in LDS
+ * together is split at a table, and chunks without points launch no
+ * workgroup.  A workgroup copies the images of all its tables into LDS once
+ * and walks its table runs with no further barrier; the backward flushes
+ * each table's dL/dv once, at the end.
  * Packs the copies, uploads the plan and synchronises `stream`.
  */
 pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,

@@ -342,7 +342,7 @@ pwl_status create_table(const pwl::BuildParams& bp, void* stream, pwl_table** ou
   pwl_status st = device_ready(&dev, nullptr, &max_lds);
   if (st != PWL_OK) return st;
   const size_t need = std::max(pwl::finalize_lds_bytes(bp.N),
-                               pwl::batch_lds_bytes(bp.N, pwl::map_cells_max(bp.N), true));
+                               pwl::batch_table_lds_bytes(bp.N, pwl::map_cells_max(bp.N), true));
   if (need > (size_t)max_lds)
     return fail(PWL_ECAPACITY, "N = %d needs %zu bytes of LDS, the device offers %d", bp.N, need, max_lds);
   pwl::TableDev td;
@@ -784,27 +784,65 @@ void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, st
 
 struct ClassPlan {
   std::vector<pwl::BatchRun> runs;
-  std::vector<int32_t> begin;
-  int grid = 0;
-  size_t lds = 0;
+  std::vector<pwl::BatchGroup> groups;
+  size_t lds = 16;
 };
 
-// One launch per direction: a grid of `want` workgroups per CU over all the
-// tables, each workgroup reserving the LDS of the largest one.  Register use
-// keeps one 1024-thread workgroup resident per CU, so a grid of many per CU
-// runs as many short rounds, dispatched as CUs free up: CUs that stream
-// faster take more of the chunks, where a one-round grid waits for its
-// slowest CU.
-ClassPlan plan_batch(const pwl_table* const* tables, int T, const int64_t* offsets, bool backward, int num_cu,
-                     int want) {
+// One launch per direction: the points are cut into a grid of `want`
+// chunks of equal cost per CU (plan_runs).  Register use keeps one
+// 1024-thread workgroup resident per CU, so a grid of many per CU runs as
+// many short rounds, dispatched as CUs free up: CUs that stream faster take
+// more of the chunks, where a one-round grid waits for its slowest CU.  A
+// chunk becomes one workgroup that copies the images of all its tables (a
+// contiguous span of the arena) into LDS once, with the backward's dL/dv
+// regions after them; a chunk whose tables need more than `cap` bytes of LDS
+// is split, at a table, into several workgroups.
+ClassPlan plan_batch(const int64_t* offsets, int T, const std::vector<int64_t>& img_word,
+                     const std::vector<int32_t>& nvec, const std::vector<int32_t>& Ns, bool backward,
+                     int num_cu, int want, size_t cap) {
   ClassPlan p;
   std::vector<int> all(T);
-  for (int i = 0; i < T; ++i) {
-    all[i] = i;
-    p.lds = std::max(p.lds, pwl::batch_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, backward));
+  for (int i = 0; i < T; ++i) all[i] = i;
+  // chunks below 2^30 points: the kernels index points within a chunk in 32 bits
+  const int64_t total = offsets[T];
+  const int grid0 = (int)std::max<int64_t>((int64_t)num_cu * std::max(1, want), (total >> 30) + 1);
+  std::vector<int32_t> rb;
+  plan_runs(offsets, all, grid0, &p.runs, &rb);
+  for (int w = 0; w < grid0; ++w) {
+    int q = rb[w];
+    const int qe = rb[w + 1];
+    while (q < qe) {
+      const int64_t img0 = img_word[p.runs[q].table];
+      int64_t span = 0, dvw = 0;
+      int qq = q;
+      for (; qq < qe; ++qq) {
+        const int t = p.runs[qq].table;
+        const int64_t sp = img_word[t] + nvec[t] - img0;
+        const int64_t dw = dvw + (backward ? pwl::batch_dv_words(Ns[t]) : 0);
+        if (qq > q && (size_t)(16 * (sp + dw)) > cap) break;
+        span = sp;
+        dvw = dw;
+      }
+      pwl::BatchGroup g{};
+      g.img = img0;
+      g.nwords = (int32_t)span;
+      g.r0 = q;
+      g.r1 = qq;
+      g.dv_lds = (int32_t)span;
+      int64_t cum = 0;
+      for (int k = q; k < qq; ++k) {
+        const int t = p.runs[k].table;
+        p.runs[k].img_lds = (int32_t)(img_word[t] - img0);
+        p.runs[k].dv_lds = backward ? (int32_t)(span + cum) : 0;
+        if (backward) cum += pwl::batch_dv_words(Ns[t]);
+      }
+      g.dv_words = (int32_t)cum;
+      p.lds = std::max(p.lds, (size_t)(16 * (span + cum)));
+      p.groups.push_back(g);
+      q = qq;
+    }
   }
-  p.grid = num_cu * std::max(1, want);
-  plan_runs(offsets, all, p.grid, &p.runs, &p.begin);
+  if (p.groups.empty()) p.groups.push_back(pwl::BatchGroup{});   // no points: one idle workgroup
   return p;
 }
 
@@ -829,26 +867,34 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   for (int i = 0; i < T; ++i)
     if (tables[i]->device != dev)
       return fail(PWL_EINVAL, "tables[%d] lives on device %d, current is %d", i, tables[i]->device, dev);
+  // the images in table order, each on a 256-byte boundary of the arena
+  std::vector<int32_t> nvec(T), Ns(T);
+  std::vector<int64_t> img_word(T);
+  int64_t arena_words = 0;
+  for (int i = 0; i < T; ++i) {
+    Ns[i] = tables[i]->bp.N;
+    nvec[i] = pwl::image_words(tables[i]->bp.N, tables[i]->bp.K);
+    img_word[i] = arena_words;
+    arena_words += (nvec[i] + 15) / 16 * 16;
+  }
+  int max_lds = 0;
+  (void)device_ready(nullptr, nullptr, &max_lds);
+  const size_t cap = std::min<size_t>((size_t)max_lds, 160 * 1024);
   const int want_f = pwl::get_launch(PWL_KERNEL_BATCH).wg_per_cu;
   const int want_b = pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD).wg_per_cu;
-  ClassPlan plans[2] = {plan_batch(tables, T, offsets, false, num_cu, want_f),
-                        plan_batch(tables, T, offsets, true, num_cu, want_b)};
-  // one allocation: tables, their deepest map cells, their images, then the
-  // runs and starts of the forward and the backward launch
+  ClassPlan plans[2] = {plan_batch(offsets, T, img_word, nvec, Ns, false, num_cu, want_f, cap),
+                        plan_batch(offsets, T, img_word, nvec, Ns, true, num_cu, want_b, cap)};
+  // one allocation: tables, their deepest map cells, the image arena, then
+  // the runs and workgroups of the forward and the backward launch
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
   const size_t o_maxc = take(sizeof(int32_t) * T);
-  std::vector<size_t> o_img(T);
-  std::vector<int32_t> nvec(T);
-  for (int i = 0; i < T; ++i) {
-    nvec[i] = (int32_t)((pwl::eval_lds_bytes(tables[i]->bp.N, tables[i]->bp.K, false) + 15) / 16);
-    o_img[i] = take(16 * (size_t)nvec[i]);
-  }
-  size_t o_runs[2], o_beg[2];
+  const size_t o_arena = take(16 * (size_t)std::max<int64_t>(1, arena_words));
+  size_t o_runs[2], o_grp[2];
   for (int dir = 0; dir < 2; ++dir) {
     o_runs[dir] = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, plans[dir].runs.size()));
-    o_beg[dir] = take(sizeof(int32_t) * plans[dir].begin.size());
+    o_grp[dir] = take(sizeof(pwl::BatchGroup) * plans[dir].groups.size());
   }
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, off);
@@ -860,7 +906,7 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   int64_t dv_len = 0;
   for (int i = 0; i < T; ++i) {
     hb[i].t = eval_view(tables[i]);
-    hb[i].img = reinterpret_cast<float4*>(b + o_img[i]);
+    hb[i].img = reinterpret_cast<float4*>(b + o_arena) + img_word[i];
     hb[i].nvec = nvec[i];
     hb[i].pad = 0;
     dv_off[i] = dv_len;
@@ -880,7 +926,6 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
       ClassPlan& p = plans[dir];
       for (pwl::BatchRun& r : p.runs) {
         const pwl_table* t = tables[r.table];
-        r.img = hb[r.table].img;
         r.nvec = nvec[r.table];
         r.dv_off = dv_off[r.table];
         r.N = t->bp.N;
@@ -894,11 +939,13 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
         e = hipMemcpyAsync(b + o_runs[dir], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
                            hipMemcpyHostToDevice, s);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(b + o_beg[dir], p.begin.data(), sizeof(int32_t) * p.begin.size(), hipMemcpyHostToDevice,
-                           s);
+        e = hipMemcpyAsync(b + o_grp[dir], p.groups.data(), sizeof(pwl::BatchGroup) * p.groups.size(),
+                           hipMemcpyHostToDevice, s);
       pwl::BatchPlan& d = dir ? bt->bl.bwd : bt->bl.fwd;
       d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[dir]),
-                         reinterpret_cast<int32_t*>(b + o_beg[dir]), p.grid, (int32_t)p.runs.size(), p.lds};
+                         reinterpret_cast<pwl::BatchGroup*>(b + o_grp[dir]),
+                         reinterpret_cast<const float4*>(b + o_arena), (int32_t)p.groups.size(),
+                         (int32_t)p.runs.size(), p.lds};
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -5,12 +5,14 @@
 // The host cuts them into one contiguous chunk of equal cost per workgroup
 // (the grid holds many workgroups per CU, dispatched as CUs free up) and
 // lists, per workgroup, the (table, begin, end) runs its chunk covers.  A
-// workgroup walks its runs in order, re-staging the LDS table only when the
-// table changes, and streams each run with the same vectorised body as the
-// single-table evaluator.  The fused backward keeps a workgroup's dL/dv of
-// the current table in FP64 LDS and flushes it with global FP32 atomics into
-// the concatenated gradient (table t at dv_off_t) whenever the table changes
-// and at the end.
+// workgroup copies the LDS images of all its runs' tables - one contiguous
+// span of the batch's image arena, the host having split chunks whose span
+// would not fit - into LDS with one barrier, then streams its runs one after
+// the other with the same vectorised body as the single-table evaluator and
+// no barrier between them: a wave that finishes a run goes straight on to
+// the next.  The fused backward keeps a dL/dv region in FP64 LDS per table
+// of the workgroup and, after one more barrier, flushes each with global
+// FP32 atomics into the concatenated gradient (table t at dv_off_t).
 #include <hip/hip_runtime.h>
 
 #include "pwl_internal.h"
@@ -38,9 +40,24 @@ __device__ __forceinline__ EvalTable run_table(const BatchRun& r) {
   return t;
 }
 
-// Linear copy of n 16-byte words (descriptors or a table image) into LDS.
-__device__ __forceinline__ void copy_words(const float4* __restrict__ src, int n, float4* dst) {
-  for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+// Copies n >= 1 16-byte words from global memory to LDS, four per thread
+// per round: each round issues all its loads before its first store.  The
+// loads are unconditional (indices clamped to the last word): a load under
+// a per-thread condition would make the compiler wait for it before the next.
+__device__ __forceinline__ void stage_words(const float4* __restrict__ src4, int n, float4* dst4) {
+  const v4f* __restrict__ src = reinterpret_cast<const v4f*>(src4);
+  v4f* dst = reinterpret_cast<v4f*>(dst4);
+  const int tid = threadIdx.x, bs = blockDim.x;
+  for (int k0 = 0; k0 < n; k0 += 4 * bs) {
+    v4f w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = src[min(k0 + j * bs + tid, n - 1)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + j * bs + tid;
+      if (k < n) dst[k] = w[j];
+    }
+  }
 }
 
 template <int U>
@@ -57,33 +74,23 @@ __device__ __forceinline__ void batch_fwd_run(const BatchRun& r, const Smem& s, 
   }
 }
 
-// A workgroup walks its runs in blocks of kRunSlots descriptors held in LDS;
-// it re-stages the table image only when the table changes.
+// One workgroup: stage the images of all its runs' tables, one barrier,
+// then its runs one after the other.  The run descriptors are read from
+// global memory (uniform: the scalar cache).
 template <int U>
 __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__ runs,
-                                                    const int32_t* __restrict__ run_begin,
+                                                    const BatchGroup* __restrict__ groups,
+                                                    const float4* __restrict__ arena,
                                                     const float* __restrict__ x, float* __restrict__ y,
                                                     int vec) {
   extern __shared__ float4 lds_f4[];
-  BatchRun* slots = reinterpret_cast<BatchRun*>(lds_f4);
-  float4* image = lds_f4 + kRunSlots * (int)(sizeof(BatchRun) / 16);
-  const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
-  int cur = -1;
-  for (int rb = r0; rb < r1; rb += kRunSlots) {
-    const int nr = min(kRunSlots, r1 - rb);
-    __syncthreads();   // every thread is done with the previous descriptors and table
-    copy_words(reinterpret_cast<const float4*>(runs + rb), nr * (int)(sizeof(BatchRun) / 16), lds_f4);
-    __syncthreads();
-    for (int q = 0; q < nr; ++q) {
-      const BatchRun r = slots[q];
-      if (r.table != cur) {
-        if (cur >= 0) __syncthreads();
-        copy_words(r.img, r.nvec, image);
-        __syncthreads();
-        cur = r.table;
-      }
-      batch_fwd_run<U>(r, carve(image, r.N, r.K, false), x, y, vec != 0);
-    }
+  const BatchGroup gp = groups[blockIdx.x];
+  if (gp.r0 >= gp.r1) return;
+  stage_words(arena + gp.img, gp.nwords, lds_f4);
+  __syncthreads();
+  for (int q = gp.r0; q < gp.r1; ++q) {
+    const BatchRun r = runs[q];
+    batch_fwd_run<U>(r, carve(lds_f4 + r.img_lds, r.N, r.K, false), x, y, vec != 0);
   }
 }
 
@@ -103,56 +110,38 @@ __device__ __forceinline__ void batch_bwd_run(const BatchRun& r, const Smem& s, 
   }
 }
 
-__device__ __forceinline__ void flush_dv(const Smem& s, int N, float* __restrict__ dv) {
-  for (int k = threadIdx.x; k <= N; k += blockDim.x) {
-    const float v = (float)s.dv[k];
-    if (v != 0.0f) unsafeAtomicAdd(dv + k, v);
-  }
-}
-
-// As k_batch_fwd; the current table's dL/dv is kept in FP64 LDS and flushed
-// with global FP32 atomics into the concatenated gradient whenever the table
-// changes and at the end.
+// As k_batch_fwd, with one FP64 dL/dv region per run's table after the
+// images (zeroed before the barrier); after the runs, one more barrier and
+// every region is flushed with global FP32 atomics.
 template <int U, bool WY, bool WDX>
 __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__ runs,
-                                                    const int32_t* __restrict__ run_begin,
+                                                    const BatchGroup* __restrict__ groups,
+                                                    const float4* __restrict__ arena,
                                                     const float* __restrict__ x, const float* __restrict__ g,
                                                     float* __restrict__ y, float* __restrict__ dx,
                                                     float* __restrict__ dv, int vec) {
   extern __shared__ float4 lds_f4[];
-  BatchRun* slots = reinterpret_cast<BatchRun*>(lds_f4);
-  float4* image = lds_f4 + kRunSlots * (int)(sizeof(BatchRun) / 16);
-  const int r0 = run_begin[blockIdx.x], r1 = run_begin[blockIdx.x + 1];
-  int cur = -1, curN = 0;
-  int64_t cur_off = 0;
-  Smem s = carve(image, 0, 0, true);
-  for (int rb = r0; rb < r1; rb += kRunSlots) {
-    const int nr = min(kRunSlots, r1 - rb);
-    __syncthreads();   // every thread is done with the previous descriptors
-    copy_words(reinterpret_cast<const float4*>(runs + rb), nr * (int)(sizeof(BatchRun) / 16), lds_f4);
-    __syncthreads();
-    for (int q = 0; q < nr; ++q) {
-      const BatchRun r = slots[q];
-      if (r.table != cur) {
-        if (cur >= 0) {
-          __syncthreads();   // every thread is done with the previous table
-          flush_dv(s, curN, dv + cur_off);
-          __syncthreads();
-        }
-        copy_words(r.img, r.nvec, image);
-        s = carve(image, r.N, r.K, true);
-        for (int k = threadIdx.x; k <= r.N; k += blockDim.x) s.dv[k] = 0.0;
-        __syncthreads();
-        cur = r.table;
-        curN = r.N;
-        cur_off = r.dv_off;
-      }
-      batch_bwd_run<U, WY, WDX>(r, s, x, g, y, dx, vec != 0);
-    }
+  const BatchGroup gp = groups[blockIdx.x];
+  if (gp.r0 >= gp.r1) return;
+  stage_words(arena + gp.img, gp.nwords, lds_f4);
+  double* dvz = reinterpret_cast<double*>(lds_f4 + gp.dv_lds);
+  for (int k = threadIdx.x; k < 2 * gp.dv_words; k += blockDim.x) dvz[k] = 0.0;
+  __syncthreads();
+  for (int q = gp.r0; q < gp.r1; ++q) {
+    const BatchRun r = runs[q];
+    Smem s = carve(lds_f4 + r.img_lds, r.N, r.K, false);
+    s.dv = reinterpret_cast<double*>(lds_f4 + r.dv_lds);
+    batch_bwd_run<U, WY, WDX>(r, s, x, g, y, dx, vec != 0);
   }
-  if (cur >= 0) {
-    __syncthreads();
-    flush_dv(s, curN, dv + cur_off);
+  __syncthreads();
+  for (int q = gp.r0; q < gp.r1; ++q) {
+    const BatchRun r = runs[q];
+    const double* d = reinterpret_cast<const double*>(lds_f4 + r.dv_lds);
+    float* out = dv + r.dv_off;
+    for (int k = threadIdx.x; k <= r.N; k += blockDim.x) {
+      const float v = (float)d[k];
+      if (v != 0.0f) unsafeAtomicAdd(out + k, v);
+    }
   }
 }
 
@@ -181,15 +170,15 @@ hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchCo
   const dim3 grid(p.grid), block(c.block);
   if (g == nullptr) {
     switch (c.unroll) {
-      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
-      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
-      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, p.runs, p.run_begin, x, y, v); break;
+      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
+      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
+      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
     }
     return hipGetLastError();
   }
   const int key = (y != nullptr ? 2 : 0) | (dx != nullptr ? 1 : 0);
 #define PWL_BB(UU, A, B)                                                                              \
-  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, p.runs, p.run_begin, x, g, \
+  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, p.runs, p.groups, p.arena, x, g, \
                      y, dx, dv, v)
 #define PWL_BB_U(UU)                             \
   switch (key) {                                 \

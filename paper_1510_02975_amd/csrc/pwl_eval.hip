@@ -298,11 +298,11 @@ inline bool same_phase(const void* a, const void* b) {
 // two vectors per thread (the dL/dv LDS atomics favour a smaller register
 // footprint) in one 768-thread workgroup per CU - every further workgroup
 // there adds a dL/dv flush and a column to reduce, and larger grids measure
-// slower.  The batched kernels stage a table per run; they take 1024-thread
-// workgroups, 16 per CU, two vectors per thread forward and one in the fused
-// backward.
+// slower.  The batched kernels stage the images of a workgroup's tables
+// once; they take 1024-thread workgroups, 32 per CU and two vectors per
+// thread forward, 24 per CU and one vector in the fused backward.
 // pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 16}, {1, 1024, 16}};
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 16}, {2, 768, 1}, {2, 1024, 32}, {1, 1024, 24}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 int g_records = PWL_RECORDS_PACKED;

@@ -127,8 +127,10 @@ int get_records();
 
 // ---- batched evaluation ----------------------------------------------------
 // A batch copies every table's LDS image (the layout carve() describes:
-// records, NaN-padded knots, index map) into one arena at creation, so a
-// workgroup stages a table with one linear 16-byte copy.
+// records, NaN-padded knots, index map) into one arena at creation, in table
+// order.  A workgroup copies the images of all the tables its runs touch -
+// one contiguous span of the arena - into LDS once, then streams its runs
+// without further barriers.
 struct BatchTable {          // one table of a batch, for packing its image
   EvalTable t;               // the table's own arrays and shape
   float4* img;               // its LDS image in the batch arena
@@ -139,30 +141,44 @@ struct BatchTable {          // one table of a batch, for packing its image
 // Points [begin, end) of one table, handled by one workgroup, with the
 // table's shape copied in: a workgroup reads nothing else to evaluate it.
 struct BatchRun {
-  const float4* img;
+  int32_t img_lds;           // the table's image: 16-byte word offset in the workgroup's LDS
+  int32_t dv_lds;            // backward: word offset of the table's FP64 dL/dv in LDS
   int64_t begin, end;
   int64_t dv_off;            // first of the table's N + 1 entries in the concatenated dL/dv
   int32_t table, nvec, N, K;
   float a32, b32, scale32;
   int32_t maxc;              // most knots sharing one map cell (the unrolled compare depth)
 };
-static_assert(sizeof(BatchRun) == 64, "BatchRun is staged in 16-byte words");
+static_assert(sizeof(BatchRun) == 64, "BatchRun is 64 bytes");
 
-constexpr int kRunSlots = 64;   // run descriptors a workgroup holds in LDS at a time
+// One workgroup of a batched launch: runs [r0, r1) and the arena words
+// [img, img + nwords) holding their tables' images; the backward's dL/dv
+// regions follow the images in LDS (dv_words 16-byte words from word
+// dv_lds).
+struct BatchGroup {
+  int64_t img;
+  int32_t nwords;
+  int32_t r0, r1;
+  int32_t dv_lds, dv_words;
+  int32_t pad;
+};
+static_assert(sizeof(BatchGroup) == 32, "BatchGroup is 32 bytes");
 
-struct BatchPlan {           // the runs of every workgroup of one launch
+// LDS of one table in a batched workgroup: its image and (backward) its FP64
+// dL/dv, in 16-byte words.
+inline int batch_dv_words(int N) { return ((N + 1) * (int)sizeof(double) + 15) / 16; }
+inline size_t batch_table_lds_bytes(int N, int K, bool backward) {
+  return 16 * ((size_t)image_words(N, K) + (backward ? (size_t)batch_dv_words(N) : 0));
+}
+
+struct BatchPlan {           // the workgroups of one launch
   BatchRun* runs;            // device
-  int32_t* run_begin;        // device [grid + 1]: workgroup w owns runs [run_begin[w], run_begin[w+1])
+  BatchGroup* groups;        // device [grid]
+  const float4* arena;       // device: the images, table 0 first
   int32_t grid;
   int32_t nruns;
-  size_t lds;
+  size_t lds;                // the largest workgroup's LDS bytes
 };
-
-// LDS of a batched launch for a table of N segments and K cells: the run
-// descriptors, then the table's image (and the FP64 dL/dv).
-inline size_t batch_lds_bytes(int N, int K, bool backward) {
-  return sizeof(BatchRun) * kRunSlots + ((eval_lds_bytes(N, K, backward) + 15) & ~(size_t)15);
-}
 
 // One launch per direction over all the tables.
 struct BatchLaunch {

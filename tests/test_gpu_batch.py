@@ -155,10 +155,11 @@ def test_batch_misaligned_and_degenerate_shapes():
                          ids=["16-per-CU", "1-per-CU"])
 def test_batch_mixed_table_sizes(shapes):
     """Tables of very different LDS footprints (N = 4096, 64, 1000), each
-    appearing several times, on a grid of 16 workgroups per CU (many rounds,
-    every workgroup reserving the largest table's LDS) and of one: the grid is
-    the configured workgroups per CU, y and dx match the per-table evaluator
-    bit for bit and dL/dv matches the oracle."""
+    appearing several times, cut for 16 workgroups per CU (many rounds) and
+    for one: a workgroup per non-empty chunk, plus one for every split of a
+    chunk whose tables' images do not fit in LDS together (at most one per
+    table); y and dx match the per-table evaluator bit for bit and dL/dv
+    matches the oracle."""
     import paper_1510_02975_amd as P
     library()
     dev = device()
@@ -180,7 +181,8 @@ def _mixed_sizes(P, dev, shapes):
     xt, gt = torch.from_numpy(x).to(dev), torch.from_numpy(g).to(dev)
     bt = P.pwl_batch_create(tabs, offs)
     say("grid fwd %d bwd %d, runs fwd %d bwd %d" % (bt.grid_fwd, bt.grid_bwd, bt.runs_fwd, bt.runs_bwd))
-    assert bt.grid_fwd == num_cu * shapes[0][2] and bt.grid_bwd == num_cu * shapes[1][2]
+    assert 1 <= bt.grid_fwd <= num_cu * shapes[0][2] + len(tabs)
+    assert 1 <= bt.grid_bwd <= num_cu * shapes[1][2] + len(tabs)
     y = P.pwl_batch_eval(bt, xt)
     yb, dxb, dvb = P.pwl_batch_eval_backward(bt, xt, gt)
     dvb = dvb.cpu().numpy()
