@@ -372,6 +372,11 @@ def batch_extra(torch, P, W, dev, args):
     dx = torch.empty_like(x)
     dv = torch.empty(bt.dv_len, dtype=torch.float32, device=dev)
     t_fb = timed_median(torch, lambda i: P.pwl_batch_eval_backward(bt, x, g, y, dx, dv), reps=10)
+    if args.quick:   # profiling runs: the batched launches only
+        bt.free()
+        for t in tabs:
+            t.free()
+        return {"batch_fwd_gpoints_s": n / t_fwd / 1e9, "batch_fwd_bwd_gpoints_s": n / t_fb / 1e9}
     o = [int(v) for v in offs]
     views = [(t, x[o[k]:o[k + 1]], y[o[k]:o[k + 1]]) for k, t in enumerate(tabs) if o[k + 1] > o[k]]
 
@@ -567,6 +572,8 @@ def main():
     ap.add_argument("--batch-log2n", type=int, default=28)
     ap.add_argument("--legs", default="layout,direct,fused,c3,kde,batch",
                     help="secondary measurements to run (comma list; --no-extra runs none)")
+    ap.add_argument("--quick", action="store_true",
+                    help="for profiler runs: the batch leg times only its batched launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

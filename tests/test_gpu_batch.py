@@ -106,6 +106,10 @@ def test_batch_graph_replays_match_eager():
     yb, dxb = torch.empty_like(xt), torch.empty_like(xt)
     dvb = torch.full((bt.dv_len,), 3.0, device=dev)
     P.pwl_batch_capture(bt, xt, yb, g=gt, dx=dxb, dv=dvb)
+    # dL/dv sums per-workgroup partials with FP32 atomics in no fixed order:
+    # two runs agree to the gradient tolerance, normwise per entry (the scale
+    # of entry k is the sum over its table's points of |g phi_k(x)|)
+    scale = np.concatenate([_abs_weights(t, x[o0:o1], g[o0:o1]) for t, o0, o1 in zip(tabs, offs[:-1], offs[1:])])
     for rep in range(4):
         dvb.fill_(float(rep + 1))              # the graph must clear dv itself
         yb.zero_()
@@ -113,8 +117,18 @@ def test_batch_graph_replays_match_eager():
         P.pwl_batch_replay(bt)
         torch.cuda.synchronize()
         assert torch.equal(yb, ye) and torch.equal(dxb, dxe), rep
-        assert torch.allclose(dvb, dve, rtol=1e-5, atol=1e-4), rep
+        diff = np.abs(dvb.cpu().numpy().astype(np.float64) - dve.cpu().numpy())
+        assert np.all(diff <= 2 * GRAD_TOL * scale + 1e-30), rep
     bt.free()
+
+
+def _abs_weights(table, x, g):
+    """Per entry k of a table's dL/dv: the sum over the points of |g| times
+    the hat weight phi_k(x), from the oracle on the table's own knots."""
+    import paper_1510_02975_amd as P
+    X = P.pwl_table_download(table)["knots"].astype(np.float64)
+    _, _, w = O.evaluate_backward(X, np.zeros(len(X)), x.astype(np.float64), np.abs(g.astype(np.float64)))
+    return w
 
 
 def test_batch_misaligned_and_degenerate_shapes():
