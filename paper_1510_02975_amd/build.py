@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpwl.so")
-SOURCES = ["pwl_api.hip", "pwl_build.hip", "pwl_eval.hip", "pwl_batch.hip", "pwl_kde.hip"]
+SOURCES = ["pwl_api.hip", "pwl_build.hip", "pwl_eval.hip", "pwl_batch.hip", "pwl_kde.hip", "pwl_baselines.hip"]
 ARCH = os.environ.get("PWL_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

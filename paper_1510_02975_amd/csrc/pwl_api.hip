@@ -782,6 +782,8 @@ void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, st
   (*run_begin)[grid] = (int32_t)runs->size();
 }
 
+constexpr int kXcds = 8;   // MI355X accelerator complex dies
+
 struct ClassPlan {
   std::vector<pwl::BatchRun> runs;
   std::vector<pwl::BatchGroup> groups;
@@ -843,6 +845,25 @@ ClassPlan plan_batch(const int64_t* offsets, int T, const std::vector<int64_t>& 
     }
   }
   if (p.groups.empty()) p.groups.push_back(pwl::BatchGroup{});   // no points: one idle workgroup
+  // Backward: workgroups are dealt to the 8 XCDs round-robin (workgroup w
+  // to XCD w mod 8), each with its own L2.  Launch index w takes chunk
+  // (w mod 8) * ceil(G / 8) + w / 8, so every XCD walks a contiguous eighth
+  // of the chunks in order: the workgroups that share a table (it spans
+  // consecutive chunks) mostly run on one XCD at nearly the same time, and
+  // all but the first read its image from that L2 and flush their dL/dv
+  // atomics into lines it holds.  Measured on the 4096-table workload: the
+  // fused backward 947 -> 940 us; the forward 418 -> 427 us at 32
+  // workgroups per CU, so it keeps the chunk order.
+  const int G = (int)p.groups.size(), per = (G + kXcds - 1) / kXcds;
+  if (backward && G >= kXcds) {
+    std::vector<pwl::BatchGroup> order;
+    order.reserve((size_t)per * kXcds);
+    for (int w = 0; w < per * kXcds; ++w) {
+      const int c = (w % kXcds) * per + w / kXcds;
+      order.push_back(c < G ? p.groups[c] : pwl::BatchGroup{});   // past the end: an idle workgroup
+    }
+    p.groups.swap(order);
+  }
   return p;
 }
 
