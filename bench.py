@@ -497,7 +497,7 @@ def layout_extra(torch, P, table, xs, ys, n):
     mode, rec = P.pwl_get_locate(), P.pwl_get_records()
     out = {}
     for lo, ln in ((P.LOCATE_MAP, "map"), (P.LOCATE_SEARCH, "search")):
-        for rc, rn in ((P.RECORDS_PACKED, "packed"), (P.RECORDS_SOA, "soa")):
+        for rc, rn in ((P.RECORDS_PACKED, "packed"), (P.RECORDS_SOA, "soa"), (P.RECORDS_PAIRS, "pairs")):
             P.pwl_set_locate(lo)
             P.pwl_set_records(rc)
             t = timed_median(torch, lambda i: P.pwl_eval(table, xs[i % len(xs)], ys[i % len(ys)]))
@@ -505,7 +505,8 @@ def layout_extra(torch, P, table, xs, ys, n):
     P.pwl_set_locate(mode)
     P.pwl_set_records(rec)
     out["fwd_layout_in_use"] = "%s_%s" % ("map" if mode == P.LOCATE_MAP else "search",
-                                          "packed" if rec == P.RECORDS_PACKED else "soa")
+                                          {P.RECORDS_PACKED: "packed", P.RECORDS_SOA: "soa",
+                                           P.RECORDS_PAIRS: "pairs"}[rec])
     return out
 
 

@@ -423,14 +423,17 @@ int32_t pwl_get_locate(void);
 
 #define PWL_RECORDS_PACKED 0  /* one 16-byte record {x_k, v_k, slope_k, x_{k+1}} per segment (default) */
 #define PWL_RECORDS_SOA 1     /* the same fields as four arrays of N floats                        */
+#define PWL_RECORDS_PAIRS 2   /* 8-byte {v_k, slope_k} pairs; x_k from the knot array              */
 
 /*
  * pwl_set_records - process-wide arrangement of the per-segment data that
  * pwl_eval stages in LDS (Sec. V discusses arranging the table for the
  * GPU's memory): packed records, where a point's lookup is one 12-byte LDS
- * read, or structure-of-arrays, where it is three 4-byte reads.  The values
- * are the same, so outputs are bit-identical; the choice is a speed A/B.
- * The fused backward, the batched kernels and pwl_kde always use packed
+ * read; structure-of-arrays, three 4-byte reads; or value/slope pairs, one
+ * 8-byte read, the segment's knot coming from the knot reads of the locate
+ * (the smallest image: 8 bytes per segment instead of 16).  The values are
+ * the same, so outputs are bit-identical; the choice is a speed A/B.  The
+ * fused backward, the batched kernels and pwl_kde always use packed
  * records.  Takes effect for later launches; pwl_get_records reads it back.
  */
 pwl_status pwl_set_records(int32_t layout);

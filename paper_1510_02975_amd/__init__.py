@@ -11,7 +11,7 @@ it has not been built.
 from .binding import (  # noqa: F401
     BESSEL_J0, EXP, FLAG_DEGENERATE, FLAG_KNOTS_COLLAPSED, FLAG_NONFINITE, GAUSSIAN, INTERP,
     KDE_EXPF, KDE_FAST_EXPF, KDE_TABLE, KERNEL_BACKWARD, KERNEL_BATCH, KERNEL_BATCH_BACKWARD, KERNEL_FORWARD,
-    LOCATE_MAP, LOCATE_SEARCH, RECORDS_PACKED, RECORDS_SOA,
+    LOCATE_MAP, LOCATE_SEARCH, RECORDS_PACKED, RECORDS_SOA, RECORDS_PAIRS,
     LORENTZIAN, MAX_N, NORM_L2,
     NORM_LINF, OPTIMAL, POLY, PROJ, SAMPLED, UNIFORM, Batch, PWLError, PWLFunction, PWLTable, Table, load_library,
     pwl_abi_version, pwl_batch_capture, pwl_batch_create, pwl_batch_eval, pwl_batch_eval_backward,

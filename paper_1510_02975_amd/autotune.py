@@ -29,7 +29,7 @@ DEFAULT_CANDIDATES = {
     "wg_per_cu": (1, 2, 4, 8, 16, 24, 32),
 }
 LOCATE_NAMES = {B.LOCATE_MAP: "map", B.LOCATE_SEARCH: "search"}
-RECORDS_NAMES = {B.RECORDS_PACKED: "packed", B.RECORDS_SOA: "soa"}
+RECORDS_NAMES = {B.RECORDS_PACKED: "packed", B.RECORDS_SOA: "soa", B.RECORDS_PAIRS: "pairs"}
 
 
 def _time(fn, reps, warm_seconds=0.05):
@@ -90,7 +90,7 @@ def tune_layout(run, reps=10, verbose=False):
     pair, its seconds and all results {(locate, records): seconds}."""
     warm_up(torch, run)
     res = {}
-    for loc, rec in itertools.product((B.LOCATE_MAP, B.LOCATE_SEARCH), (B.RECORDS_PACKED, B.RECORDS_SOA)):
+    for loc, rec in itertools.product((B.LOCATE_MAP, B.LOCATE_SEARCH), tuple(RECORDS_NAMES)):
         B.pwl_set_locate(loc)
         B.pwl_set_records(rec)
         res[loc, rec] = _time(run, reps)

@@ -476,7 +476,7 @@ def pwl_get_launch(kernel):
 
 
 LOCATE_MAP, LOCATE_SEARCH = 0, 1
-RECORDS_PACKED, RECORDS_SOA = 0, 1
+RECORDS_PACKED, RECORDS_SOA, RECORDS_PAIRS = 0, 1, 2
 KDE_TABLE, KDE_EXPF, KDE_FAST_EXPF = 0, 1, 2
 
 

@@ -48,16 +48,21 @@ __device__ __forceinline__ void eval_fwd_body(const EvalTable& t, const S& s, co
   }
 }
 
-// SOA selects the structure-of-arrays records (PWL_RECORDS_SOA) instead of
-// the packed ones.
-template <int U, bool SOA>
+// REC is the arrangement of the per-segment data in LDS (pwl_set_records):
+// packed records, structure of arrays, or value/slope pairs.
+template <int U, int REC>
 __global__ __launch_bounds__(1024) void k_eval_fwd(EvalTable t, const float* __restrict__ vo,
                                                    const float* __restrict__ x,
                                                    float* __restrict__ y, int64_t n, int flags) {
   extern __shared__ float4 lds_f4[];
-  if constexpr (SOA) {
+  if constexpr (REC == PWL_RECORDS_SOA) {
     const SmemSoA s = carve_soa(lds_f4, t.N, t.K);
     stage_table(t, vo, s);
+    __syncthreads();
+    eval_fwd_body<U>(t, s, x, y, n, flags);
+  } else if constexpr (REC == PWL_RECORDS_PAIRS) {
+    const SmemPairs s = carve_pairs(lds_f4, t.N, t.K);
+    stage_table_pairs(t, vo, s);
     __syncthreads();
     eval_fwd_body<U>(t, s, x, y, n, flags);
   } else {
@@ -236,7 +241,8 @@ hipError_t set_locate(int mode) {
 int get_locate() { return g_locate; }
 
 hipError_t set_records(int layout) {
-  if (layout != PWL_RECORDS_PACKED && layout != PWL_RECORDS_SOA) return hipErrorInvalidValue;
+  if (layout != PWL_RECORDS_PACKED && layout != PWL_RECORDS_SOA && layout != PWL_RECORDS_PAIRS)
+    return hipErrorInvalidValue;
   g_records = layout;
   return hipSuccess;
 }
@@ -247,25 +253,28 @@ hipError_t launch_eval(const EvalTable& t, const float* vo, const float* x, floa
                        int num_cu, hipStream_t s) {
   const bool vec = same_phase(x, y) && (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const LaunchConfig c = g_launch[0];
-  const bool soa = g_records == PWL_RECORDS_SOA;
-  const size_t lds = soa ? eval_lds_bytes_soa(t.N, t.K) : eval_lds_bytes(t.N, t.K, false);
+  const int rec = g_records;
+  const size_t lds = rec == PWL_RECORDS_SOA     ? eval_lds_bytes_soa(t.N, t.K)
+                     : rec == PWL_RECORDS_PAIRS ? eval_lds_bytes_pairs(t.N, t.K)
+                                                : eval_lds_bytes(t.N, t.K, false);
   const LaunchShape ls = stream_shape(c, lds, vec ? n / 4 : 0, n, num_cu);
   const int v = (vec ? 1 : 0) | (g_locate == PWL_LOCATE_SEARCH ? 2 : 0);
-#define PWL_FWD(UU, SS) \
-  hipLaunchKernelGGL((k_eval_fwd<UU, SS>), dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v)
-  if (soa) {
-    switch (c.unroll) {
-      case 1: PWL_FWD(1, true); break;
-      case 2: PWL_FWD(2, true); break;
-      default: PWL_FWD(4, true); break;
-    }
-  } else {
-    switch (c.unroll) {
-      case 1: PWL_FWD(1, false); break;
-      case 2: PWL_FWD(2, false); break;
-      default: PWL_FWD(4, false); break;
-    }
+#define PWL_FWD(UU, RR) \
+  hipLaunchKernelGGL((k_eval_fwd<UU, RR>), dim3(ls.grid), dim3(ls.block), ls.lds, s, t, vo, x, y, n, v)
+#define PWL_FWD_U(RR)                   \
+  switch (c.unroll) {                   \
+    case 1: PWL_FWD(1, RR); break;      \
+    case 2: PWL_FWD(2, RR); break;      \
+    default: PWL_FWD(4, RR); break;     \
   }
+  if (rec == PWL_RECORDS_SOA) {
+    PWL_FWD_U(PWL_RECORDS_SOA)
+  } else if (rec == PWL_RECORDS_PAIRS) {
+    PWL_FWD_U(PWL_RECORDS_PAIRS)
+  } else {
+    PWL_FWD_U(PWL_RECORDS_PACKED)
+  }
+#undef PWL_FWD_U
 #undef PWL_FWD
   return hipGetLastError();
 }
@@ -349,12 +358,14 @@ hipError_t configure_eval_kernels(int max_lds) {
   e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, lim);    \
   if (e != hipSuccess) return e;
   PWL_ATTR(k_locate)
-  PWL_ATTR((k_eval_fwd<1, false>))
-  PWL_ATTR((k_eval_fwd<2, false>))
-  PWL_ATTR((k_eval_fwd<4, false>))
-  PWL_ATTR((k_eval_fwd<1, true>))
-  PWL_ATTR((k_eval_fwd<2, true>))
-  PWL_ATTR((k_eval_fwd<4, true>))
+#define PWL_ATTR_R(RR)                   \
+  PWL_ATTR((k_eval_fwd<1, RR>))          \
+  PWL_ATTR((k_eval_fwd<2, RR>))          \
+  PWL_ATTR((k_eval_fwd<4, RR>))
+  PWL_ATTR_R(PWL_RECORDS_PACKED)
+  PWL_ATTR_R(PWL_RECORDS_SOA)
+  PWL_ATTR_R(PWL_RECORDS_PAIRS)
+#undef PWL_ATTR_R
 #define PWL_ATTR_U(U)                            \
   PWL_ATTR((k_eval_bwd<U, false, false, true>))  \
   PWL_ATTR((k_eval_bwd<U, false, true, false>))  \

@@ -91,6 +91,11 @@ inline size_t eval_lds_bytes(int N, int K, bool backward) {
 }
 
 inline size_t eval_lds_bytes_soa(int N, int K) { return 16 * (size_t)image_words_soa(N, K); }
+// The value/slope-pairs variant (forward only): two 8-byte pairs per word.
+__host__ __device__ inline int image_pair_words(int N) { return (N + 1) / 2; }
+inline size_t eval_lds_bytes_pairs(int N, int K) {
+  return 16 * (size_t)(image_pair_words(N) + image_knot_words(N) + image_map_words(K));
+}
 
 // Table finalize: 4 FP64 PCR rows, the FP32 knots and their u16 map cells.
 inline size_t finalize_lds_bytes(int N) {

@@ -44,6 +44,17 @@ struct SmemSoA {
   }
 };
 
+// Value/slope pairs: one 8-byte pair {v_k, slope_k} per segment, with x_k
+// read from the knot array, whose entry 0 holds a (no compare reads entry 0,
+// so it can): a point reads its map cell, the knots of its cell with the one
+// before them (the segment's own knot among them; adjacent, so one paired
+// read for a cell of one knot) and one pair.  Forward evaluation only.
+struct SmemPairs {
+  float2* vs;       // [N]        {v_k, slope_k}
+  float* knot;      // [N + pad]  knot[0] = a, knot[k] = x_k for 1 <= k <= N-1, NaN from N on
+  uint16_t* lo;
+};
+
 // Sections of a table image (see image_words).  Every pointer is an offset
 // from `base` itself: a pointer rebuilt from an integer would lose its
 // address space, and LDS accesses (the dL/dv atomics above all) would go
@@ -68,6 +79,18 @@ __device__ __forceinline__ SmemSoA carve_soa(void* base, int N, int K) {
   s.rs = reinterpret_cast<float*>(b4 + 2 * fw);
   s.rw = reinterpret_cast<float*>(b4 + 3 * fw);
   s.knot = reinterpret_cast<float*>(b4 + 4 * fw);
+  s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
+  (void)K;
+  return s;
+}
+
+// The pairs image: the pairs (two per 16-byte word), then the knots and the
+// map as in carve.
+__device__ __forceinline__ SmemPairs carve_pairs(void* base, int N, int K) {
+  SmemPairs s;
+  float4* b4 = reinterpret_cast<float4*>(base);
+  s.vs = reinterpret_cast<float2*>(b4);
+  s.knot = reinterpret_cast<float*>(b4 + image_pair_words(N));
   s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
   (void)K;
   return s;
@@ -98,6 +121,13 @@ __device__ __forceinline__ float4 knot_word(const EvalTable& t, int w) {
     e[i] = (k >= 1 && k <= t.N - 1) ? t.knots[k] : __builtin_nanf("");
   }
   return make_float4(e[0], e[1], e[2], e[3]);
+}
+
+// The same with entry 0 = a (the pairs image):
+__device__ __forceinline__ float4 knot_word_a(const EvalTable& t, int w) {
+  float4 k = knot_word(t, w);
+  if (w == 0) k.x = t.a32;
+  return k;
 }
 
 // map entries 8w .. 8w+7, 0 past lo[K]:
@@ -138,6 +168,39 @@ __device__ __forceinline__ void stage_table(const EvalTable& t, const float* __r
   }
   for (int w = tid; w < t.N; w += nt) s.put_record(w, record_word(t, vo, w));
   for (int w = tid; w < nkw; w += nt) knot4[w] = knot_word(t, w);
+  for (int w = tid; w < nmw; w += nt) map4[w] = map_word(t, w);
+}
+
+// The pairs image: word w holds the pairs of segments 2w and 2w + 1 (zero
+// past N - 1); sections as in stage_table, each in one round of loads when
+// it fits in one word per thread.
+__device__ __forceinline__ float4 pair_word(const EvalTable& t, const float* __restrict__ vo, int w) {
+  const float4 r0 = record_word(t, vo, 2 * w);
+  float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (2 * w + 1 < t.N) r1 = record_word(t, vo, 2 * w + 1);
+  return make_float4(r0.y, r0.z, r1.y, r1.z);
+}
+
+__device__ __forceinline__ void stage_table_pairs(const EvalTable& t, const float* __restrict__ vo,
+                                                  const SmemPairs& s) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int npw = image_pair_words(t.N), nkw = image_knot_words(t.N), nmw = image_map_words(t.K);
+  float4* pair4 = reinterpret_cast<float4*>(s.vs);
+  float4* knot4 = reinterpret_cast<float4*>(s.knot);
+  float4* map4 = reinterpret_cast<float4*>(s.lo);
+  if (npw <= nt && nkw <= nt && nmw <= nt) {
+    const bool hp = tid < npw, hk = tid < nkw, hm = tid < nmw;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f), k = p, m = p;
+    if (hp) p = pair_word(t, vo, tid);
+    if (hk) k = knot_word_a(t, tid);
+    if (hm) m = map_word(t, tid);
+    if (hp) pair4[tid] = p;
+    if (hk) knot4[tid] = k;
+    if (hm) map4[tid] = m;
+    return;
+  }
+  for (int w = tid; w < npw; w += nt) pair4[w] = pair_word(t, vo, w);
+  for (int w = tid; w < nkw; w += nt) knot4[w] = knot_word_a(t, w);
   for (int w = tid; w < nmw; w += nt) map4[w] = map_word(t, w);
 }
 
@@ -198,6 +261,35 @@ __device__ __forceinline__ float eval_point(float x, const EvalTable& t, const S
   const int seg = locate<MAXC>(x, t, s);
   const float4 r = s.record(seg);
   return fmaf(clamp_nan(x, t.a32, t.b32) - r.x, r.z, r.y);
+}
+
+// Algorithm 1 through the pairs image.  With MAXC unrolled compares the
+// segment's knot comes out of the compares themselves (the last knot of the
+// cell that x reaches, or the knot before the cell), so the knot reads are
+// adjacent; otherwise it is read after the locate.  The same operations on
+// the same values as eval_point, so the outputs are bit-identical.
+template <int MAXC>
+__device__ __forceinline__ float eval_point(float x, const EvalTable& t, const SmemPairs& s) {
+  int seg;
+  float xs;
+  if (MAXC > 0) {
+    const int u = map_cell(x, t.a32, t.scale32, t.K);
+    const int lo = s.lo[u];
+    seg = lo;
+    xs = s.knot[lo];
+#pragma unroll
+    for (int j = 1; j <= MAXC; ++j) {
+      const float kj = s.knot[lo + j];
+      const bool c = x >= kj;
+      seg += c ? 1 : 0;
+      xs = c ? kj : xs;
+    }
+  } else {
+    seg = locate<MAXC>(x, t, s);
+    xs = s.knot[seg];
+  }
+  const float2 p = s.vs[seg];
+  return fmaf(clamp_nan(x, t.a32, t.b32) - xs, p.y, p.x);
 }
 
 template <int MAXC, bool WY, bool WDX, bool WDV>

@@ -3,9 +3,9 @@
 each against the FP64 oracle: both must return the oracle's segment index
 (Algorithm 1, step 1) on the GPU's own knots, exactly, and pwl_eval through
 either must match the oracle's evaluation; the two modes' outputs are then
-bit-identical.  The same for the two arrangements of the per-segment data
-in LDS (packed records and structure of arrays, Sec. V), under both locate
-modes.  Points: random, every knot and its FP32 neighbours, the domain ends,
+bit-identical.  The same for the three arrangements of the per-segment
+data in LDS (packed records, structure of arrays, value/slope pairs;
+Sec. V), under both locate modes.  Points: random, every knot and its FP32 neighbours, the domain ends,
 points outside, +-inf and NaN."""
 
 import numpy as np
@@ -75,9 +75,10 @@ def test_binary_search_locate_matches_index_map(spec):
 
 @pytest.mark.parametrize("spec", TABLES)
 def test_record_layouts_match_oracle(spec):
-    """Structure-of-arrays records against the oracle and bit-identical to
-    the packed ones, with the index map and with the binary search; also on
-    the scalar (misaligned) path and with a vertex-value override."""
+    """Structure-of-arrays records and value/slope pairs against the oracle
+    and bit-identical to the packed records, with the index map and with the
+    binary search; also on the scalar (misaligned) path and with a
+    vertex-value override."""
     import paper_1510_02975_amd as P
     library()
     dev = device()
@@ -89,21 +90,22 @@ def test_record_layouts_match_oracle(spec):
     Xg, vg = d["knots"].astype(np.float64), d["values"].astype(np.float64)
     vo = torch.from_numpy((1.0 + 0.5 * np.cos(np.arange(N + 1))).astype(np.float32)).to(dev)
     out = {}
-    for rec in (P.RECORDS_PACKED, P.RECORDS_SOA):
+    for rec in (P.RECORDS_PACKED, P.RECORDS_SOA, P.RECORDS_PAIRS):
         for mode in (P.LOCATE_MAP, P.LOCATE_SEARCH):
             with records_layout(P, rec), locate_mode(P, mode):
                 out[rec, mode] = (P.pwl_eval(t, x).cpu().numpy(), P.pwl_eval(t, x[1:4000]).cpu().numpy(),
                                   P.pwl_eval(t, x, v_override=vo).cpu().numpy())
-    say("  f=%d N=%d: %d points, 4 variants" % (func, N, x.numel()))
+    say("  f=%d N=%d: %d points, 6 variants" % (func, N, x.numel()))
     fin = ~np.isnan(xh)
     y_ref = O.evaluate(Xg, vg, xh.astype(np.float64))
     scale = fmax_abs(func, p, a, b)
-    y_soa = out[P.RECORDS_SOA, P.LOCATE_MAP][0]
-    assert np.array_equal(np.isnan(y_soa), np.isnan(y_ref))
-    assert np.max(np.abs(y_soa[fin] - y_ref[fin])) <= Y_TOL * scale
     y_vo_ref = O.evaluate(Xg, vo.cpu().numpy().astype(np.float64), xh.astype(np.float64))
-    y_vo = out[P.RECORDS_SOA, P.LOCATE_MAP][2]
-    assert np.max(np.abs(y_vo[fin] - y_vo_ref[fin])) <= 4e-6 * 1.5
+    for rec in (P.RECORDS_SOA, P.RECORDS_PAIRS):
+        y_rec = out[rec, P.LOCATE_MAP][0]
+        assert np.array_equal(np.isnan(y_rec), np.isnan(y_ref))
+        assert np.max(np.abs(y_rec[fin] - y_ref[fin])) <= Y_TOL * scale
+        y_vo = out[rec, P.LOCATE_MAP][2]
+        assert np.max(np.abs(y_vo[fin] - y_vo_ref[fin])) <= 4e-6 * 1.5
     base = out[P.RECORDS_PACKED, P.LOCATE_MAP]
     for key, val in out.items():
         for a_, b_ in zip(base, val):
