@@ -398,7 +398,7 @@ pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const vo
  * can be resident at once if asked (later ones start as earlier ones end).
  * The single-table kernels cut the grid back, a whole workgroup per compute
  * unit at a time and to no fewer than one per compute unit, until each
- * workgroup streams at least 2^16 points and 2 points per byte of the table
+ * workgroup streams at least 2^15 points and 2 points per byte of the table
  * it stages in LDS.  All three
  * zero restores the default.  Used by the autotuner; takes effect for later
  * launches.

@@ -24,7 +24,7 @@ namespace {
 
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kXcds = 8;             // MI355X accelerator complex dies; workgroups go to them round-robin
-constexpr int64_t kMinPointsPerWG = int64_t(1) << 16;   // streaming grids: points per workgroup, at least
+constexpr int64_t kMinPointsPerWG = int64_t(1) << 15;   // streaming grids: points per workgroup, at least
 constexpr int64_t kPointsPerStagedByte = 2;             // and per byte of table the workgroup stages
 
 using namespace stream;
@@ -190,8 +190,9 @@ inline bool same_phase(const void* a, const void* b) {
 // of table it stages, but never below one workgroup per CU (nor above one
 // per iteration of work).  The defaults are the autotuner's choice on
 // MI355X: forward at 2^28 points, four vectors per thread in 1024-thread
-// workgroups, up to 16 per CU (12 to 24 measure alike at N = 1024; at
-// N = 4096 the staging rule leaves about 3); fused backward at 2^26 points,
+// workgroups, up to 24 per CU (at N = 1024 the staging rule leaves 18,
+// which measured 333 us against 335 us for 16; at N = 4096 it leaves about
+// 3); fused backward at 2^26 points,
 // two vectors per thread (the dL/dv LDS atomics favour a smaller register
 // footprint) in one 768-thread workgroup per CU - every further workgroup
 // there adds a dL/dv flush and a column to reduce, and larger grids measure
