@@ -289,14 +289,21 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
  *                new batch to be seen).
  *   offsets[T+1] HOST array, offsets[0] = 0, non-decreasing (empty tables
  *                allowed); offsets[T] is the total number of points.
- * Each direction is one launch.  The points are cut into the workgroups
- * per CU of the PWL_KERNEL_BATCH (forward) or PWL_KERNEL_BATCH_BACKWARD
- * launch shape current at creation, one contiguous chunk of equal cost per
- * workgroup (a table switch costs as much as 4096 points); a chunk whose
- * tables' LDS images (and, backward, their FP64 dL/dv) do not fit in LDS
- * together is split at a table, and chunks without points launch no
- * workgroup.  A workgroup copies the images of all its tables into LDS once
- * and walks its table runs with no further barrier; the backward flushes
+ * Each direction is one launch, planned for the PWL_KERNEL_BATCH (forward)
+ * or PWL_KERNEL_BATCH_BACKWARD launch shape current at creation.
+ * Forward: the points are cut into slices of two of the kernel's vector
+ * iterations (unroll * block * 8 points) from point 0 on, whatever the
+ * tables; a slice whose tables' LDS images do not fit together is split at
+ * a table.  The grid holds wg_per_cu workgroups per CU (fewer if there are
+ * fewer slices) and workgroup b takes slices b, b + grid, ...: per slice it
+ * copies the images of the slice's tables into LDS and streams the slice as
+ * one range, each wave with the table of its points.
+ * Backward: the points are cut into wg_per_cu workgroups per CU, one
+ * contiguous chunk of equal cost per workgroup (a table switch costs as
+ * much as 4096 points); a chunk whose tables' images and FP64 dL/dv do not
+ * fit in LDS together is split at a table, and chunks without points
+ * launch no workgroup.  A workgroup copies the images of all its tables
+ * into LDS once, walks its table runs with no further barrier and flushes
  * each table's dL/dv once, at the end.
  * Packs the copies, uploads the plan and synchronises `stream`.
  */
@@ -328,7 +335,8 @@ pwl_status pwl_batch_replay(pwl_batch* bt, void* stream);
 
 /*
  * pwl_batch_info - shape of a batch (outputs nullable): tables, points, dv
- * length, and per direction the workgroups and table runs of its launch.
+ * length, and per direction the workgroups and table runs of its launch
+ * (the forward's runs: one per table per slice it meets).
  */
 pwl_status pwl_batch_info(const pwl_batch* bt, int32_t* T, int64_t* npoints, int64_t* dv_len, int32_t* grid_fwd,
                           int32_t* grid_bwd, int32_t* runs_fwd, int32_t* runs_bwd);
@@ -396,6 +404,8 @@ pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const vo
  * workgroups have `block` threads (a multiple of 64 in [64, 1024]) and the
  * grid holds up to `wg_per_cu` (1..32) of them per compute unit, more than
  * can be resident at once if asked (later ones start as earlier ones end).
+ * The batched forward's grid is persistent: its workgroups take the
+ * batch's slices round-robin.
  * The single-table kernels cut the grid back, a whole workgroup per compute
  * unit at a time and to no fewer than one per compute unit, until each
  * workgroup streams at least 2^15 points and 2 points per byte of the table

@@ -783,6 +783,7 @@ void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, st
 }
 
 constexpr int kXcds = 8;   // MI355X accelerator complex dies
+constexpr int kSliceIterations = 2;   // vector iterations per forward slice
 
 struct ClassPlan {
   std::vector<pwl::BatchRun> runs;
@@ -867,6 +868,52 @@ ClassPlan plan_batch(const int64_t* offsets, int T, const std::vector<int64_t>& 
   return p;
 }
 
+// Forward: the points in slices of `slice` points from point 0 on (the last
+// one shorter), each slice the runs of the tables it meets; a slice whose
+// images need more than `cap` bytes of LDS becomes several groups, split at
+// a table.  The kernel deals the groups to its workgroups round-robin.
+ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>& img_word,
+                      const std::vector<int32_t>& nvec, int64_t slice, size_t cap) {
+  ClassPlan p;
+  const int64_t total = offsets[T];
+  auto close = [&](int q, int64_t img0) {
+    const int q1 = (int)p.runs.size();
+    if (q1 == q) return;
+    const int last = p.runs[q1 - 1].table;
+    pwl::BatchGroup g{};
+    g.img = img0;
+    g.nwords = (int32_t)(img_word[last] + nvec[last] - img0);
+    g.r0 = q;
+    g.r1 = q1;
+    for (int k = q; k < q1; ++k) p.runs[k].img_lds = (int32_t)(img_word[p.runs[k].table] - img0);
+    p.lds = std::max(p.lds, (size_t)(16 * (size_t)g.nwords));
+    p.groups.push_back(g);
+  };
+  int t0 = 0;
+  for (int64_t s0 = 0; s0 < total; s0 += slice) {
+    const int64_t s1 = std::min(total, s0 + slice);
+    while (offsets[t0 + 1] <= s0) ++t0;   // the table holding point s0
+    int q = (int)p.runs.size();
+    int64_t img0 = -1;
+    for (int u = t0; u < T && offsets[u] < s1; ++u) {
+      if (offsets[u + 1] == offsets[u]) continue;   // no points
+      if (img0 >= 0 && (size_t)(16 * (img_word[u] + nvec[u] - img0)) > cap) {
+        close(q, img0);
+        q = (int)p.runs.size();
+        img0 = -1;
+      }
+      if (img0 < 0) img0 = img_word[u];
+      pwl::BatchRun r{};
+      r.table = u;
+      r.begin = std::max(s0, offsets[u]);
+      r.end = std::min(s1, offsets[u + 1]);
+      p.runs.push_back(r);
+    }
+    close(q, img0);
+  }
+  return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -901,10 +948,14 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   int max_lds = 0;
   (void)device_ready(nullptr, nullptr, &max_lds);
   const size_t cap = std::min<size_t>((size_t)max_lds, 160 * 1024);
-  const int want_f = pwl::get_launch(PWL_KERNEL_BATCH).wg_per_cu;
+  const pwl::LaunchConfig cf = pwl::get_launch(PWL_KERNEL_BATCH);
   const int want_b = pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD).wg_per_cu;
-  ClassPlan plans[2] = {plan_batch(offsets, T, img_word, nvec, Ns, false, num_cu, want_f, cap),
+  // forward slices: two vector iterations of the forward kernel's current shape
+  const int64_t slice = (int64_t)kSliceIterations * 4 * cf.block * cf.unroll;
+  ClassPlan plans[2] = {plan_slices(offsets, T, img_word, nvec, slice, cap),
                         plan_batch(offsets, T, img_word, nvec, Ns, true, num_cu, want_b, cap)};
+  const int64_t ng = (int64_t)plans[0].groups.size();
+  const int grid_f = (int)std::max<int64_t>(1, std::min<int64_t>(ng, (int64_t)num_cu * std::max(1, cf.wg_per_cu)));
   // one allocation: tables, their deepest map cells, the image arena, then
   // the runs and workgroups of the forward and the backward launch
   size_t off = 0;
@@ -915,7 +966,7 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   size_t o_runs[2], o_grp[2];
   for (int dir = 0; dir < 2; ++dir) {
     o_runs[dir] = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, plans[dir].runs.size()));
-    o_grp[dir] = take(sizeof(pwl::BatchGroup) * plans[dir].groups.size());
+    o_grp[dir] = take(sizeof(pwl::BatchGroup) * std::max<size_t>(1, plans[dir].groups.size()));
   }
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, off);
@@ -956,16 +1007,21 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
         r.scale32 = t->bp.scale32;
         r.maxc = maxc[r.table];
       }
+      for (pwl::BatchGroup& g : p.groups) {
+        g.maxc = 0;
+        for (int k = g.r0; k < g.r1; ++k) g.maxc = std::max(g.maxc, p.runs[k].maxc);
+      }
       if (e == hipSuccess && !p.runs.empty())
         e = hipMemcpyAsync(b + o_runs[dir], p.runs.data(), sizeof(pwl::BatchRun) * p.runs.size(),
                            hipMemcpyHostToDevice, s);
-      if (e == hipSuccess)
+      if (e == hipSuccess && !p.groups.empty())
         e = hipMemcpyAsync(b + o_grp[dir], p.groups.data(), sizeof(pwl::BatchGroup) * p.groups.size(),
                            hipMemcpyHostToDevice, s);
       pwl::BatchPlan& d = dir ? bt->bl.bwd : bt->bl.fwd;
+      const int32_t ngroups = (int32_t)p.groups.size();
       d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[dir]),
                          reinterpret_cast<pwl::BatchGroup*>(b + o_grp[dir]),
-                         reinterpret_cast<const float4*>(b + o_arena), (int32_t)p.groups.size(),
+                         reinterpret_cast<const float4*>(b + o_arena), dir ? ngroups : grid_f, ngroups,
                          (int32_t)p.runs.size(), p.lds};
     }
   }

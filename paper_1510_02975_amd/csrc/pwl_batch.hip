@@ -2,17 +2,27 @@
 // in one launch.
 //
 // The points of all tables are concatenated (table t owns [off_t, off_{t+1})).
-// The host cuts them into one contiguous chunk of equal cost per workgroup
-// (the grid holds many workgroups per CU, dispatched as CUs free up) and
-// lists, per workgroup, the (table, begin, end) runs its chunk covers.  A
-// workgroup copies the LDS images of all its runs' tables - one contiguous
-// span of the batch's image arena, the host having split chunks whose span
-// would not fit - into LDS with one barrier, then streams its runs one after
-// the other with the same vectorised body as the single-table evaluator and
-// no barrier between them: a wave that finishes a run goes straight on to
-// the next.  The fused backward keeps a dL/dv region in FP64 LDS per table
-// of the workgroup and, after one more barrier, flushes each with global
-// FP32 atomics into the concatenated gradient (table t at dv_off_t).
+//
+// Forward: the host cuts the points into slices of a whole number of the
+// kernel's vector iterations (two by default) at fixed positions of the
+// concatenated arrays, whatever the tables, and lists per slice the
+// (table, begin, end) runs it covers; a slice whose tables' LDS images
+// would not fit is split at a table.  A grid of a few workgroups per CU
+// takes the slices round-robin (workgroup b: slices b, b + grid, ...), so
+// the workgroups in flight stream neighbouring slices and every slice is
+// streamed in full iterations: a slice boundary, not a table boundary, ends
+// an iteration.  Per slice a workgroup copies its tables' images (one
+// contiguous span of the batch's image arena) into LDS, passes a barrier and
+// streams the slice as one range; each wave looks up the run of its
+// 64 vectors (scalar: the slice's runs are in order) and, where the vectors
+// cross a table boundary, evaluates each point with its own table.
+//
+// Fused backward: the host cuts the points into one contiguous chunk of
+// equal cost per workgroup and lists the chunk's runs; the workgroup stages
+// its tables' images and one FP64 dL/dv region per table in LDS, streams its
+// runs one after the other with the single-table evaluator's body, and after
+// one more barrier flushes each region with global FP32 atomics into the
+// concatenated gradient (table t at dv_off_t).
 #include <hip/hip_runtime.h>
 
 #include "pwl_internal.h"
@@ -60,37 +70,157 @@ __device__ __forceinline__ void stage_words(const float4* __restrict__ src4, int
   }
 }
 
-template <int U>
-__device__ __forceinline__ void batch_fwd_run(const BatchRun& r, const Smem& s, const float* __restrict__ x,
-                                              float* __restrict__ y, bool vec) {
-  const EvalTable t = run_table(r);
-  switch (r.maxc) {
-    case 0:
-    case 1: fwd_run<U, 1>(t, s, x, y, r.begin, r.end, vec); break;
-    case 2: fwd_run<U, 2>(t, s, x, y, r.begin, r.end, vec); break;
-    case 3: fwd_run<U, 3>(t, s, x, y, r.begin, r.end, vec); break;
-    case 4: fwd_run<U, 4>(t, s, x, y, r.begin, r.end, vec); break;
-    default: fwd_run<U, 0>(t, s, x, y, r.begin, r.end, vec); break;
+// A workgroup barrier that orders LDS accesses only: the streaming stores a
+// wave still has in flight are not waited for (__syncthreads would).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Run q of a slice: its points and its table, whose image is in LDS.  q is
+// uniform, so the descriptor comes through the scalar cache.
+struct RunView {
+  EvalTable t;
+  Smem s;
+  int64_t begin, end;
+};
+
+__device__ __forceinline__ RunView run_view(const BatchRun* __restrict__ runs, int q, float4* lds) {
+  const BatchRun r = runs[q];
+  RunView v;
+  v.t = run_table(r);
+  v.s = carve(lds + r.img_lds, r.N, r.K, false);
+  v.begin = r.begin;
+  v.end = r.end;
+  return v;
+}
+
+template <int MAXC>
+__device__ __forceinline__ v4f eval4(const v4f& xv, const RunView& v) {
+  v4f yv;
+  yv.x = eval_point<MAXC>(xv.x, v.t, v.s);
+  yv.y = eval_point<MAXC>(xv.y, v.t, v.s);
+  yv.z = eval_point<MAXC>(xv.z, v.t, v.s);
+  yv.w = eval_point<MAXC>(xv.w, v.t, v.s);
+  return yv;
+}
+
+// Points [lo, hi) of runs [r0, r1) one by one (the unaligned ends of a
+// slice, or every point when the arrays cannot be read as vectors).
+template <int MAXC>
+__device__ __forceinline__ void slice_scalar(const BatchRun* __restrict__ runs, int r0, int r1, float4* lds,
+                                             const float* __restrict__ x, float* __restrict__ y, int64_t lo,
+                                             int64_t hi) {
+  if (lo >= hi) return;
+  for (int q = r0; q < r1; ++q) {
+    const RunView v = run_view(runs, q, lds);
+    const int64_t a = v.begin > lo ? v.begin : lo, b = v.end < hi ? v.end : hi;
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) y[i] = eval_point<MAXC>(x[i], v.t, v.s);
   }
 }
 
-// One workgroup: stage the images of all its runs' tables, one barrier,
-// then its runs one after the other.  The run descriptors are read from
-// global memory (uniform: the scalar cache).
+// One iteration of a slice: U vectors per thread, vectors ib + tid + u bs.
+// Loads, then lookups, then stores, as in the single-table body.  The 64
+// vectors of a wave (points pf .. pf + 255) take the run `cur`, advanced to
+// the one holding pf; a wave whose points reach past it evaluates each
+// point under the run it falls in, for the runs up to the wave's last point.
+template <int U, int MAXC, bool GUARD>
+__device__ __forceinline__ void slice_iter(const BatchRun* __restrict__ runs, int r1, float4* lds, RunView& cur,
+                                           int& q, const v4f* __restrict__ x4, v4f* __restrict__ y4,
+                                           int64_t ib, int64_t vend, int64_t phase, int64_t e, int tid,
+                                           int wave0) {
+  const int64_t bs = blockDim.x;
+  v4f xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = ib + tid + u * bs;
+    if (!GUARD || i < vend) xv[u] = __builtin_nontemporal_load(x4 + i);
+  }
+  v4f yv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t w = ib + wave0 + u * bs;   // the wave's first vector
+    if (GUARD && w >= vend) continue;       // no lane of the wave has a vector here
+    const int64_t pf = 4 * w - phase;
+    const int64_t pl = (pf + 255 < e - 1) ? pf + 255 : e - 1;
+    while (cur.end <= pf && q + 1 < r1) cur = run_view(runs, ++q, lds);
+    if (pl < cur.end) {
+      yv[u] = eval4<MAXC>(xv[u], cur);
+    } else {
+      const int64_t p0 = 4 * (ib + tid + u * bs) - phase;   // this lane's first point
+      v4f out = xv[u];
+      RunView v = cur;
+      for (int qq = q;;) {
+        if (p0 >= v.begin && p0 < v.end) out.x = eval_point<MAXC>(xv[u].x, v.t, v.s);
+        if (p0 + 1 >= v.begin && p0 + 1 < v.end) out.y = eval_point<MAXC>(xv[u].y, v.t, v.s);
+        if (p0 + 2 >= v.begin && p0 + 2 < v.end) out.z = eval_point<MAXC>(xv[u].z, v.t, v.s);
+        if (p0 + 3 >= v.begin && p0 + 3 < v.end) out.w = eval_point<MAXC>(xv[u].w, v.t, v.s);
+        if (v.end > pl || qq + 1 >= r1) break;
+        v = run_view(runs, ++qq, lds);
+      }
+      yv[u] = out;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = ib + tid + u * bs;
+    if (!GUARD || i < vend) __builtin_nontemporal_store(yv[u], y4 + i);
+  }
+}
+
+// A slice: runs [r0, r1), points [runs[r0].begin, runs[r1-1].end), their
+// images staged at the runs' img_lds.
+template <int U, int MAXC>
+__device__ __forceinline__ void slice_fwd(const BatchRun* __restrict__ runs, int r0, int r1, float4* lds,
+                                          const float* __restrict__ x, float* __restrict__ y, bool vec,
+                                          int wave0) {
+  const int64_t b = runs[r0].begin, e = runs[r1 - 1].end;
+  const Split sp = split_range(x, b, e, vec);
+  if (sp.vend <= sp.vbeg) {
+    slice_scalar<MAXC>(runs, r0, r1, lds, x, y, b, e);
+    return;
+  }
+  const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
+  const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x - phase);
+  v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y - phase);
+  const int tid = threadIdx.x;
+  const int64_t chunk = (int64_t)blockDim.x * U;
+  int q = r0;
+  RunView cur = run_view(runs, q, lds);
+  int64_t ib = sp.vbeg;
+  for (; ib + chunk <= sp.vend; ib += chunk)
+    slice_iter<U, MAXC, false>(runs, r1, lds, cur, q, x4, y4, ib, sp.vend, phase, e, tid, wave0);
+  if (ib < sp.vend) slice_iter<U, MAXC, true>(runs, r1, lds, cur, q, x4, y4, ib, sp.vend, phase, e, tid, wave0);
+  slice_scalar<MAXC>(runs, r0, r1, lds, x, y, b, sp.head);
+  const int64_t tail = 4 * sp.vend - phase;
+  slice_scalar<MAXC>(runs, r0, r1, lds, x, y, tail > sp.head ? tail : sp.head, e);
+}
+
+// Slices blockIdx.x, blockIdx.x + gridDim.x, ...: stage the slice's images,
+// one barrier, stream it; one more barrier before the next slice's images
+// overwrite LDS.
 template <int U>
 __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__ runs,
-                                                    const BatchGroup* __restrict__ groups,
+                                                    const BatchGroup* __restrict__ groups, int ngroups,
                                                     const float4* __restrict__ arena,
                                                     const float* __restrict__ x, float* __restrict__ y,
                                                     int vec) {
   extern __shared__ float4 lds_f4[];
-  const BatchGroup gp = groups[blockIdx.x];
-  if (gp.r0 >= gp.r1) return;
-  stage_words(arena + gp.img, gp.nwords, lds_f4);
-  __syncthreads();
-  for (int q = gp.r0; q < gp.r1; ++q) {
-    const BatchRun r = runs[q];
-    batch_fwd_run<U>(r, carve(lds_f4 + r.img_lds, r.N, r.K, false), x, y, vec != 0);
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
+  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const BatchGroup gp = groups[gi];
+    if (gi != (int)blockIdx.x) lds_barrier();
+    stage_words(arena + gp.img, gp.nwords, lds_f4);
+    lds_barrier();
+    switch (gp.maxc) {
+      case 0:
+      case 1: slice_fwd<U, 1>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
+      case 2: slice_fwd<U, 2>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
+      case 3: slice_fwd<U, 3>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
+      case 4: slice_fwd<U, 4>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
+      default: slice_fwd<U, 0>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
+    }
   }
 }
 
@@ -170,9 +300,9 @@ hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchCo
   const dim3 grid(p.grid), block(c.block);
   if (g == nullptr) {
     switch (c.unroll) {
-      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
-      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
-      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, p.runs, p.groups, p.arena, x, y, v); break;
+      case 1: hipLaunchKernelGGL(k_batch_fwd<1>, grid, block, p.lds, s, p.runs, p.groups, p.ngroups, p.arena, x, y, v); break;
+      case 2: hipLaunchKernelGGL(k_batch_fwd<2>, grid, block, p.lds, s, p.runs, p.groups, p.ngroups, p.arena, x, y, v); break;
+      default: hipLaunchKernelGGL(k_batch_fwd<4>, grid, block, p.lds, s, p.runs, p.groups, p.ngroups, p.arena, x, y, v); break;
     }
     return hipGetLastError();
   }

@@ -156,16 +156,16 @@ struct BatchRun {
 };
 static_assert(sizeof(BatchRun) == 64, "BatchRun is 64 bytes");
 
-// One workgroup of a batched launch: runs [r0, r1) and the arena words
+// One work unit of a batched launch: runs [r0, r1) and the arena words
 // [img, img + nwords) holding their tables' images; the backward's dL/dv
 // regions follow the images in LDS (dv_words 16-byte words from word
-// dv_lds).
+// dv_lds).  maxc: the deepest map cell among its runs' tables.
 struct BatchGroup {
   int64_t img;
   int32_t nwords;
   int32_t r0, r1;
   int32_t dv_lds, dv_words;
-  int32_t pad;
+  int32_t maxc;
 };
 static_assert(sizeof(BatchGroup) == 32, "BatchGroup is 32 bytes");
 
@@ -176,13 +176,14 @@ inline size_t batch_table_lds_bytes(int N, int K, bool backward) {
   return 16 * ((size_t)image_words(N, K) + (backward ? (size_t)batch_dv_words(N) : 0));
 }
 
-struct BatchPlan {           // the workgroups of one launch
+struct BatchPlan {           // the work units of one launch
   BatchRun* runs;            // device
-  BatchGroup* groups;        // device [grid]
+  BatchGroup* groups;        // device [ngroups]
   const float4* arena;       // device: the images, table 0 first
-  int32_t grid;
+  int32_t grid;              // workgroups launched (the forward's take groups grid apart, the backward's one each)
+  int32_t ngroups;
   int32_t nruns;
-  size_t lds;                // the largest workgroup's LDS bytes
+  size_t lds;                // the largest group's LDS bytes
 };
 
 // One launch per direction over all the tables.

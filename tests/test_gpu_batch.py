@@ -165,6 +165,56 @@ def test_batch_misaligned_and_degenerate_shapes():
     bt.free()
 
 
+@pytest.mark.parametrize("shape", [(4, 1024, 3), (1, 256, 1), (2, 512, 8)], ids=["u4", "u1-256", "u2-512"])
+def test_batch_forward_slices_cross_tables(shape):
+    """The forward's slices against table boundaries: runs of 1 to 300
+    points (a wave's 256 points then cross several tables, and a vector
+    holds points of up to four), tables of N = 16 .. 4096 (different
+    unrolled compare depths in one slice), and a stretch of N = 4096
+    tables with 97 points each, whose images cannot share LDS, so its
+    slices are split at every table; x and y at every 4-byte phase.  Every
+    table's points match pwl_eval bit for bit."""
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    rng = np.random.default_rng(11)
+    kinds = [(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0), (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0),
+             (O.BESSEL_J0, (1.0,), 0.0, 50.0)]
+    built = {}
+
+    def table(k, N):
+        if (k, N) not in built:
+            f, p, a, b = kinds[k]
+            built[k, N] = P.pwl_build(f, p, a, b, N, O.OPTIMAL if N % 2 else O.UNIFORM, O.PROJ)
+        return built[k, N]
+    tabs, counts = [], []
+    for i in range(600):
+        tabs.append(table(i % 3, int(rng.choice([16, 33, 200, 1000, 4096]))))
+        counts.append(int(rng.integers(1, 301)))
+    for i in range(40):
+        tabs.append(table(i % 3, 4096))
+        counts.append(97)
+    for i in range(30):
+        tabs.append(table(i % 3, int(rng.choice([64, 777]))))
+        counts.append(int(rng.integers(0, 70000)))
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n = int(offs[-1])
+    base = torch.from_numpy(W.uniform_points(-25.0, 55.0, n + 8, 12)).to(dev)
+    with launch_shape(P, P.KERNEL_BATCH, shape):
+        bt = P.pwl_batch_create(tabs, offs)
+        say("%d tables, %d points, shape %s: grid %d, %d runs" % (len(tabs), n, shape, bt.grid_fwd, bt.runs_fwd))
+        for ph in (0, 1, 2, 3):
+            x = base[ph:ph + n]
+            y = torch.full((n + 8,), 7.0, device=dev)[(ph * 3) % 4:(ph * 3) % 4 + n]
+            P.pwl_batch_eval(bt, x, y)
+            ref = torch.cat([P.pwl_eval(t, x[o0:o1]) for t, o0, o1 in zip(tabs, offs[:-1], offs[1:])])
+            bad = torch.nonzero(y != ref).flatten()
+            assert bad.numel() == 0, (ph, int(np.searchsorted(offs, int(bad[0]), side="right")) - 1)
+        bt.free()
+    for t in built.values():
+        t.free()
+
+
 @pytest.mark.parametrize("shapes", [((2, 1024, 16), (1, 1024, 16)), ((4, 1024, 1), (2, 512, 1))],
                          ids=["16-per-CU", "1-per-CU"])
 def test_batch_mixed_table_sizes(shapes):
