@@ -298,13 +298,11 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
  * fewer slices) and workgroup b takes slices b, b + grid, ...: per slice it
  * copies the images of the slice's tables into LDS and streams the slice as
  * one range, each wave with the table of its points.
- * Backward: the points are cut into wg_per_cu workgroups per CU, one
- * contiguous chunk of equal cost per workgroup (a table switch costs as
- * much as 4096 points); a chunk whose tables' images and FP64 dL/dv do not
- * fit in LDS together is split at a table, and chunks without points
- * launch no workgroup.  A workgroup copies the images of all its tables
- * into LDS once, walks its table runs with no further barrier and flushes
- * each table's dL/dv once, at the end.
+ * Backward: the same, in slices of its own launch shape; per slice the
+ * workgroup also sums every point's hat weights into one FP64 dL/dv region
+ * per table in LDS and stores each region, rounded to FP32, as that run's
+ * N + 1 partial sums in a buffer the batch owns; a second kernel adds each
+ * table's partial sums in slice order in FP64.
  * Packs the copies, uploads the plan and synchronises `stream`.
  */
 pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int64_t* offsets, void* stream,
@@ -317,7 +315,10 @@ pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream)
  * pwl_batch_eval_backward - fused forward + backward for every table: y and
  * dx (each nullable) as in pwl_eval_backward; g is required unless the
  * batch has no points; dv (required) is the concatenation of every table's
- * N_t + 1 gradients, table t first, and is OVERWRITTEN.
+ * N_t + 1 gradients, table t first, and is OVERWRITTEN (zero for tables
+ * without points).  dv is summed in a fixed order, so repeated calls give
+ * the same bits.  The partial sums live in the batch: calls on one batch
+ * must not overlap (on different streams, or with a replay of its graph).
  */
 pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g, float* y, float* dx,
                                    float* dv, void* stream);

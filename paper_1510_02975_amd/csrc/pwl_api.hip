@@ -727,63 +727,12 @@ pwl_status pwl_kde(const pwl_table* t, int32_t mode, const void* frame, const vo
 
 namespace {
 
-// Cost of a table switch in points streamed: a switch (barriers, staging
-// the image, the run's ragged ends) takes a workgroup a few microseconds.
-// Weights of 0, 2048 and 16384 measured slower than this one on the
-// 4096-table workload.
-constexpr int64_t kStagePoints = 4096;
-
-// Runs of one launch over the tables listed in `cls` (increasing table
-// order).  Their work, taken in that order, is cut into `grid` chunks
-// of equal cost, where a table with points costs kStagePoints (its staging)
-// plus its points, so a workgroup that meets many small tables gets fewer
-// points.  A chunk boundary inside a table is rounded down to a multiple of
-// 4 points of the global arrays (not below the table's first point), so
-// chunks keep the arrays' 16-byte phase.
-void plan_runs(const int64_t* offsets, const std::vector<int>& cls, int grid, std::vector<pwl::BatchRun>* runs,
-               std::vector<int32_t>* run_begin) {
-  runs->clear();
-  run_begin->assign(grid + 1, 0);
-  const int C = (int)cls.size();
-  std::vector<int64_t> voff(C + 1, 0);   // cumulative cost
-  for (int j = 0; j < C; ++j) {
-    const int64_t pts = offsets[cls[j] + 1] - offsets[cls[j]];
-    voff[j + 1] = voff[j] + (pts > 0 ? kStagePoints + pts : 0);
-  }
-  const int64_t total = voff[C];
-  if (total == 0) return;
-  // boundary w: listed table bj[w] at absolute point bp[w]; bj[grid] = C is the end
-  std::vector<int> bj(grid + 1, C);
-  std::vector<int64_t> bp(grid + 1, 0);
-  int j = 0;
-  for (int w = 0; w < grid; ++w) {
-    const int64_t v = (int64_t)((__int128)total * w / grid);   // < total
-    while (voff[j + 1] <= v) ++j;                                // skips tables without points
-    const int64_t first = offsets[cls[j]];
-    const int64_t q = v - voff[j] - kStagePoints;                 // points of table j before the boundary
-    bj[w] = j;
-    bp[w] = (q <= 0) ? first : std::max(first, (first + q) & ~(int64_t)3);
-  }
-  for (int w = 0; w < grid; ++w) {
-    (*run_begin)[w] = (int32_t)runs->size();
-    for (int jj = bj[w]; jj < C && jj <= bj[w + 1]; ++jj) {
-      const int u = cls[jj];
-      const int64_t b0 = (jj == bj[w]) ? bp[w] : offsets[u];
-      const int64_t e0 = (jj == bj[w + 1]) ? bp[w + 1] : offsets[u + 1];
-      if (b0 < e0) {
-        pwl::BatchRun r{};
-        r.table = u;
-        r.begin = b0;
-        r.end = e0;
-        runs->push_back(r);
-      }
-    }
-  }
-  (*run_begin)[grid] = (int32_t)runs->size();
-}
-
-constexpr int kXcds = 8;   // MI355X accelerator complex dies
-constexpr int kSliceIterations = 2;   // vector iterations per forward slice
+// Vector iterations per slice, forward and backward.  Longer slices stage
+// less often but stream worse: on the 4096-table workload the forward
+// measured fastest at 2 (3: +1%, 4: +6%), the fused backward at 4 (2: +10%,
+// 8: +2%), and slices lengthened in proportion to their table's LDS bytes
+// (to stage big tables less often) slower still.
+constexpr int kSliceIterations[2] = {2, 4};
 
 struct ClassPlan {
   std::vector<pwl::BatchRun> runs;
@@ -791,92 +740,19 @@ struct ClassPlan {
   size_t lds = 16;
 };
 
-// One launch per direction: the points are cut into a grid of `want`
-// chunks of equal cost per CU (plan_runs).  Register use keeps one
-// 1024-thread workgroup resident per CU, so a grid of many per CU runs as
-// many short rounds, dispatched as CUs free up: CUs that stream faster take
-// more of the chunks, where a one-round grid waits for its slowest CU.  A
-// chunk becomes one workgroup that copies the images of all its tables (a
-// contiguous span of the arena) into LDS once, with the backward's dL/dv
-// regions after them; a chunk whose tables need more than `cap` bytes of LDS
-// is split, at a table, into several workgroups.
-ClassPlan plan_batch(const int64_t* offsets, int T, const std::vector<int64_t>& img_word,
-                     const std::vector<int32_t>& nvec, const std::vector<int32_t>& Ns, bool backward,
-                     int num_cu, int want, size_t cap) {
-  ClassPlan p;
-  std::vector<int> all(T);
-  for (int i = 0; i < T; ++i) all[i] = i;
-  // chunks below 2^30 points: the kernels index points within a chunk in 32 bits
-  const int64_t total = offsets[T];
-  const int grid0 = (int)std::max<int64_t>((int64_t)num_cu * std::max(1, want), (total >> 30) + 1);
-  std::vector<int32_t> rb;
-  plan_runs(offsets, all, grid0, &p.runs, &rb);
-  for (int w = 0; w < grid0; ++w) {
-    int q = rb[w];
-    const int qe = rb[w + 1];
-    while (q < qe) {
-      const int64_t img0 = img_word[p.runs[q].table];
-      int64_t span = 0, dvw = 0;
-      int qq = q;
-      for (; qq < qe; ++qq) {
-        const int t = p.runs[qq].table;
-        const int64_t sp = img_word[t] + nvec[t] - img0;
-        const int64_t dw = dvw + (backward ? pwl::batch_dv_words(Ns[t]) : 0);
-        if (qq > q && (size_t)(16 * (sp + dw)) > cap) break;
-        span = sp;
-        dvw = dw;
-      }
-      pwl::BatchGroup g{};
-      g.img = img0;
-      g.nwords = (int32_t)span;
-      g.r0 = q;
-      g.r1 = qq;
-      g.dv_lds = (int32_t)span;
-      int64_t cum = 0;
-      for (int k = q; k < qq; ++k) {
-        const int t = p.runs[k].table;
-        p.runs[k].img_lds = (int32_t)(img_word[t] - img0);
-        p.runs[k].dv_lds = backward ? (int32_t)(span + cum) : 0;
-        if (backward) cum += pwl::batch_dv_words(Ns[t]);
-      }
-      g.dv_words = (int32_t)cum;
-      p.lds = std::max(p.lds, (size_t)(16 * (span + cum)));
-      p.groups.push_back(g);
-      q = qq;
-    }
-  }
-  if (p.groups.empty()) p.groups.push_back(pwl::BatchGroup{});   // no points: one idle workgroup
-  // Backward: workgroups are dealt to the 8 XCDs round-robin (workgroup w
-  // to XCD w mod 8), each with its own L2.  Launch index w takes chunk
-  // (w mod 8) * ceil(G / 8) + w / 8, so every XCD walks a contiguous eighth
-  // of the chunks in order: the workgroups that share a table (it spans
-  // consecutive chunks) mostly run on one XCD at nearly the same time, and
-  // all but the first read its image from that L2 and flush their dL/dv
-  // atomics into lines it holds.  Measured on the 4096-table workload: the
-  // fused backward 947 -> 940 us; the forward 418 -> 427 us at 32
-  // workgroups per CU, so it keeps the chunk order.
-  const int G = (int)p.groups.size(), per = (G + kXcds - 1) / kXcds;
-  if (backward && G >= kXcds) {
-    std::vector<pwl::BatchGroup> order;
-    order.reserve((size_t)per * kXcds);
-    for (int w = 0; w < per * kXcds; ++w) {
-      const int c = (w % kXcds) * per + w / kXcds;
-      order.push_back(c < G ? p.groups[c] : pwl::BatchGroup{});   // past the end: an idle workgroup
-    }
-    p.groups.swap(order);
-  }
-  return p;
-}
-
-// Forward: the points in slices of `slice` points from point 0 on (the last
-// one shorter), each slice the runs of the tables it meets; a slice whose
-// images need more than `cap` bytes of LDS becomes several groups, split at
-// a table.  The kernel deals the groups to its workgroups round-robin.
+// The points in slices of `slice` points from point 0 on (the last one
+// shorter), each slice the runs of the tables it meets.  A slice whose
+// tables need more than `cap` bytes of LDS together - their images, a
+// contiguous span of the arena, and (backward) one FP64 dL/dv region per
+// table after them - becomes several groups, split at a table.  The kernels
+// deal the groups to their workgroups round-robin.
 ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>& img_word,
-                      const std::vector<int32_t>& nvec, int64_t slice, size_t cap) {
+                      const std::vector<int32_t>& nvec, const std::vector<int32_t>& Ns, bool backward,
+                      int64_t slice, size_t cap) {
   ClassPlan p;
   const int64_t total = offsets[T];
-  auto close = [&](int q, int64_t img0) {
+  auto dvw = [&](int u) { return backward ? (int64_t)pwl::batch_dv_words(Ns[u]) : 0; };
+  auto close = [&](int q, int64_t img0, int64_t dv_words) {
     const int q1 = (int)p.runs.size();
     if (q1 == q) return;
     const int last = p.runs[q1 - 1].table;
@@ -885,8 +761,16 @@ ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>&
     g.nwords = (int32_t)(img_word[last] + nvec[last] - img0);
     g.r0 = q;
     g.r1 = q1;
-    for (int k = q; k < q1; ++k) p.runs[k].img_lds = (int32_t)(img_word[p.runs[k].table] - img0);
-    p.lds = std::max(p.lds, (size_t)(16 * (size_t)g.nwords));
+    g.dv_lds = g.nwords;
+    g.dv_words = (int32_t)dv_words;
+    int64_t cum = 0;
+    for (int k = q; k < q1; ++k) {
+      pwl::BatchRun& r = p.runs[k];
+      r.img_lds = (int32_t)(img_word[r.table] - img0);
+      r.dv_lds = backward ? (int32_t)(g.nwords + cum) : 0;
+      cum += dvw(r.table);
+    }
+    p.lds = std::max(p.lds, (size_t)(16 * ((size_t)g.nwords + (size_t)dv_words)));
     p.groups.push_back(g);
   };
   int t0 = 0;
@@ -894,22 +778,24 @@ ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>&
     const int64_t s1 = std::min(total, s0 + slice);
     while (offsets[t0 + 1] <= s0) ++t0;   // the table holding point s0
     int q = (int)p.runs.size();
-    int64_t img0 = -1;
+    int64_t img0 = -1, dv_words = 0;
     for (int u = t0; u < T && offsets[u] < s1; ++u) {
       if (offsets[u + 1] == offsets[u]) continue;   // no points
-      if (img0 >= 0 && (size_t)(16 * (img_word[u] + nvec[u] - img0)) > cap) {
-        close(q, img0);
+      if (img0 >= 0 && (size_t)(16 * (img_word[u] + nvec[u] - img0 + dv_words + dvw(u))) > cap) {
+        close(q, img0, dv_words);
         q = (int)p.runs.size();
         img0 = -1;
+        dv_words = 0;
       }
       if (img0 < 0) img0 = img_word[u];
+      dv_words += dvw(u);
       pwl::BatchRun r{};
       r.table = u;
       r.begin = std::max(s0, offsets[u]);
       r.end = std::min(s1, offsets[u + 1]);
       p.runs.push_back(r);
     }
-    close(q, img0);
+    close(q, img0, dv_words);
   }
   return p;
 }
@@ -948,16 +834,37 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   int max_lds = 0;
   (void)device_ready(nullptr, nullptr, &max_lds);
   const size_t cap = std::min<size_t>((size_t)max_lds, 160 * 1024);
-  const pwl::LaunchConfig cf = pwl::get_launch(PWL_KERNEL_BATCH);
-  const int want_b = pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD).wg_per_cu;
-  // forward slices: two vector iterations of the forward kernel's current shape
-  const int64_t slice = (int64_t)kSliceIterations * 4 * cf.block * cf.unroll;
-  ClassPlan plans[2] = {plan_slices(offsets, T, img_word, nvec, slice, cap),
-                        plan_batch(offsets, T, img_word, nvec, Ns, true, num_cu, want_b, cap)};
-  const int64_t ng = (int64_t)plans[0].groups.size();
-  const int grid_f = (int)std::max<int64_t>(1, std::min<int64_t>(ng, (int64_t)num_cu * std::max(1, cf.wg_per_cu)));
-  // one allocation: tables, their deepest map cells, the image arena, then
-  // the runs and workgroups of the forward and the backward launch
+  // slices of whole vector iterations of each kernel's current shape; a
+  // persistent grid of wg_per_cu workgroups per CU (no more than slices)
+  const pwl::LaunchConfig cfg[2] = {pwl::get_launch(PWL_KERNEL_BATCH), pwl::get_launch(PWL_KERNEL_BATCH_BACKWARD)};
+  ClassPlan plans[2];
+  int grids[2];
+  for (int dir = 0; dir < 2; ++dir) {
+    const int64_t slice = (int64_t)kSliceIterations[dir] * 4 * cfg[dir].block * cfg[dir].unroll;
+    plans[dir] = plan_slices(offsets, T, img_word, nvec, Ns, dir == 1, slice, cap);
+    const int64_t ng = (int64_t)plans[dir].groups.size();
+    grids[dir] = (int)std::max<int64_t>(1, std::min<int64_t>(ng, (int64_t)num_cu * std::max(1, cfg[dir].wg_per_cu)));
+  }
+  // the backward's partial dL/dv sums: N + 1 per run; per table its runs'
+  // offsets in slice order, and its range of the concatenated gradient
+  std::vector<int64_t> tab_dv(T + 1, 0);
+  for (int i = 0; i < T; ++i) tab_dv[i + 1] = tab_dv[i] + Ns[i] + 1;
+  std::vector<int32_t> tab_first(T + 1, 0);
+  int64_t part_len = 0;
+  for (pwl::BatchRun& r : plans[1].runs) {
+    r.part = part_len;
+    part_len += Ns[r.table] + 1;
+    ++tab_first[r.table + 1];
+  }
+  for (int i = 0; i < T; ++i) tab_first[i + 1] += tab_first[i];
+  std::vector<int64_t> tab_part(std::max<size_t>(1, plans[1].runs.size()));
+  {
+    std::vector<int32_t> fill(tab_first.begin(), tab_first.end() - 1);
+    for (const pwl::BatchRun& r : plans[1].runs) tab_part[fill[r.table]++] = r.part;
+  }
+  // one allocation: tables, their deepest map cells, the image arena, the
+  // runs and work units of the forward and the backward launch, then the
+  // backward's partial sums and their per-table lists
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += align256(bytes); return o; };
   const size_t o_tab = take(sizeof(pwl::BatchTable) * T);
@@ -968,21 +875,21 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
     o_runs[dir] = take(sizeof(pwl::BatchRun) * std::max<size_t>(1, plans[dir].runs.size()));
     o_grp[dir] = take(sizeof(pwl::BatchGroup) * std::max<size_t>(1, plans[dir].groups.size()));
   }
+  const size_t o_part = take(sizeof(float) * (size_t)std::max<int64_t>(1, part_len));
+  const size_t o_tpart = take(sizeof(int64_t) * tab_part.size());
+  const size_t o_tfirst = take(sizeof(int32_t) * (T + 1));
+  const size_t o_tdv = take(sizeof(int64_t) * (T + 1));
   void* base = nullptr;
   hipError_t e = hipMalloc(&base, off);
   if (e != hipSuccess) return fail(PWL_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
   char* b = static_cast<char*>(base);
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<pwl::BatchTable> hb(T);
-  std::vector<int64_t> dv_off(T);
-  int64_t dv_len = 0;
   for (int i = 0; i < T; ++i) {
     hb[i].t = eval_view(tables[i]);
     hb[i].img = reinterpret_cast<float4*>(b + o_arena) + img_word[i];
     hb[i].nvec = nvec[i];
     hb[i].pad = 0;
-    dv_off[i] = dv_len;
-    dv_len += tables[i]->bp.N + 1;
   }
   // images and deepest cells on the device, the cells back to the host
   std::vector<int32_t> maxc(T, 0);
@@ -999,7 +906,6 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
       for (pwl::BatchRun& r : p.runs) {
         const pwl_table* t = tables[r.table];
         r.nvec = nvec[r.table];
-        r.dv_off = dv_off[r.table];
         r.N = t->bp.N;
         r.K = t->bp.K;
         r.a32 = t->bp.a32;
@@ -1021,10 +927,16 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
       const int32_t ngroups = (int32_t)p.groups.size();
       d = pwl::BatchPlan{reinterpret_cast<pwl::BatchRun*>(b + o_runs[dir]),
                          reinterpret_cast<pwl::BatchGroup*>(b + o_grp[dir]),
-                         reinterpret_cast<const float4*>(b + o_arena), dir ? ngroups : grid_f, ngroups,
+                         reinterpret_cast<const float4*>(b + o_arena), grids[dir], ngroups,
                          (int32_t)p.runs.size(), p.lds};
     }
   }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + o_tpart, tab_part.data(), sizeof(int64_t) * tab_part.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + o_tfirst, tab_first.data(), sizeof(int32_t) * (T + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + o_tdv, tab_dv.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     (void)hipFree(base);
@@ -1035,7 +947,13 @@ pwl_status pwl_batch_create(const pwl_table* const* tables, int32_t T, const int
   bt->T = T;
   bt->npoints = offsets[T];
   bt->base = base;
-  bt->bl.dv_len = dv_len;
+  bt->bl.dv_len = tab_dv[T];
+  bt->bl.T = T;
+  bt->bl.max_n = *std::max_element(Ns.begin(), Ns.end());
+  bt->bl.part = reinterpret_cast<float*>(b + o_part);
+  bt->bl.tab_part = reinterpret_cast<const int64_t*>(b + o_tpart);
+  bt->bl.tab_first = reinterpret_cast<const int32_t*>(b + o_tfirst);
+  bt->bl.tab_dv = reinterpret_cast<const int64_t*>(b + o_tdv);
   *out = bt;
   return PWL_OK;
 }

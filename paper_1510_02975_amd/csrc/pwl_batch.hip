@@ -17,12 +17,12 @@
 // 64 vectors (scalar: the slice's runs are in order) and, where the vectors
 // cross a table boundary, evaluates each point with its own table.
 //
-// Fused backward: the host cuts the points into one contiguous chunk of
-// equal cost per workgroup and lists the chunk's runs; the workgroup stages
-// its tables' images and one FP64 dL/dv region per table in LDS, streams its
-// runs one after the other with the single-table evaluator's body, and after
-// one more barrier flushes each region with global FP32 atomics into the
-// concatenated gradient (table t at dv_off_t).
+// Fused backward: the same, in slices of four iterations, with one FP64
+// dL/dv region per table of the slice in LDS after the images.  After the
+// slice the workgroup stores every region, rounded to FP32, as that run's
+// partial sums in a buffer of the batch; k_batch_dv_reduce then adds each
+// table's partial sums in slice order, in FP64, so dL/dv does not depend on
+// the order in which the workgroups ran.
 #include <hip/hip_runtime.h>
 
 #include "pwl_internal.h"
@@ -86,11 +86,13 @@ struct RunView {
   int64_t begin, end;
 };
 
+template <bool DV = false>
 __device__ __forceinline__ RunView run_view(const BatchRun* __restrict__ runs, int q, float4* lds) {
   const BatchRun r = runs[q];
   RunView v;
   v.t = run_table(r);
   v.s = carve(lds + r.img_lds, r.N, r.K, false);
+  if (DV) v.s.dv = reinterpret_cast<double*>(lds + r.dv_lds);
   v.begin = r.begin;
   v.end = r.end;
   return v;
@@ -224,54 +226,181 @@ __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__
   }
 }
 
-template <int U, bool WY, bool WDX>
-__device__ __forceinline__ void batch_bwd_run(const BatchRun& r, const Smem& s, const float* __restrict__ x,
-                                              const float* __restrict__ g, float* __restrict__ y,
-                                              float* __restrict__ dx, bool vec) {
-  using B = Bwd<U, WY, WDX, true>;
-  const EvalTable t = run_table(r);
-  switch (r.maxc) {
-    case 0:
-    case 1: B::template range<1>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
-    case 2: B::template range<2>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
-    case 3: B::template range<3>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
-    case 4: B::template range<4>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
-    default: B::template range<0>(t, s, x, g, y, dx, r.begin, r.end, vec, 0, 1); break;
+// The fused backward of a slice, as slice_fwd: x and g in, y and dx out
+// (each optional), every point's two hat weights into its run's FP64 dL/dv
+// region in LDS.  Lanes past the slice's vectors take no point (their
+// weights would be added).
+template <int MAXC, bool WY, bool WDX>
+__device__ __forceinline__ void bwd_point(float xv, float gv, const RunView& v, float& yv, float& dxv) {
+  backward_point<MAXC, WY, WDX, true>(xv, gv, v.t, v.s, yv, dxv);
+}
+
+template <int MAXC, bool WY, bool WDX>
+__device__ __forceinline__ void slice_bwd_scalar(const BatchRun* __restrict__ runs, int r0, int r1, float4* lds,
+                                                 const float* __restrict__ x, const float* __restrict__ g,
+                                                 float* __restrict__ y, float* __restrict__ dx, int64_t lo,
+                                                 int64_t hi) {
+  if (lo >= hi) return;
+  for (int q = r0; q < r1; ++q) {
+    const RunView v = run_view<true>(runs, q, lds);
+    const int64_t a = v.begin > lo ? v.begin : lo, b = v.end < hi ? v.end : hi;
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+      float yy = 0.0f, dd = 0.0f;
+      bwd_point<MAXC, WY, WDX>(x[i], g[i], v, yy, dd);
+      if (WY) y[i] = yy;
+      if (WDX) dx[i] = dd;
+    }
   }
 }
 
-// As k_batch_fwd, with one FP64 dL/dv region per run's table after the
-// images (zeroed before the barrier); after the runs, one more barrier and
-// every region is flushed with global FP32 atomics.
+template <int U, int MAXC, bool GUARD, bool WY, bool WDX>
+__device__ __forceinline__ void slice_bwd_iter(const BatchRun* __restrict__ runs, int r1, float4* lds,
+                                               RunView& cur, int& q, const v4f* __restrict__ x4,
+                                               const v4f* __restrict__ g4, v4f* __restrict__ y4,
+                                               v4f* __restrict__ dx4, int64_t ib, int64_t vend, int64_t phase,
+                                               int64_t e, int tid, int wave0) {
+  const int64_t bs = blockDim.x;
+  v4f xv[U], gv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = ib + tid + u * bs;
+    if (!GUARD || i < vend) {
+      xv[u] = __builtin_nontemporal_load(x4 + i);
+      gv[u] = __builtin_nontemporal_load(g4 + i);
+    }
+  }
+  v4f yv[U], dxv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t w = ib + wave0 + u * bs;
+    if (GUARD && w >= vend) continue;
+    const int64_t pf = 4 * w - phase;
+    const int64_t pl = (pf + 255 < e - 1) ? pf + 255 : e - 1;
+    while (cur.end <= pf && q + 1 < r1) cur = run_view<true>(runs, ++q, lds);
+    if (GUARD && ib + tid + u * bs >= vend) continue;   // this lane has no vector here
+    float yy = 0.0f, dd = 0.0f;
+    if (pl < cur.end) {
+      bwd_point<MAXC, WY, WDX>(xv[u].x, gv[u].x, cur, yy, dd); yv[u].x = yy; dxv[u].x = dd;
+      bwd_point<MAXC, WY, WDX>(xv[u].y, gv[u].y, cur, yy, dd); yv[u].y = yy; dxv[u].y = dd;
+      bwd_point<MAXC, WY, WDX>(xv[u].z, gv[u].z, cur, yy, dd); yv[u].z = yy; dxv[u].z = dd;
+      bwd_point<MAXC, WY, WDX>(xv[u].w, gv[u].w, cur, yy, dd); yv[u].w = yy; dxv[u].w = dd;
+    } else {
+      const int64_t p0 = 4 * (ib + tid + u * bs) - phase;
+      RunView v = cur;
+      for (int qq = q;;) {
+        if (p0 >= v.begin && p0 < v.end) { bwd_point<MAXC, WY, WDX>(xv[u].x, gv[u].x, v, yy, dd); yv[u].x = yy; dxv[u].x = dd; }
+        if (p0 + 1 >= v.begin && p0 + 1 < v.end) { bwd_point<MAXC, WY, WDX>(xv[u].y, gv[u].y, v, yy, dd); yv[u].y = yy; dxv[u].y = dd; }
+        if (p0 + 2 >= v.begin && p0 + 2 < v.end) { bwd_point<MAXC, WY, WDX>(xv[u].z, gv[u].z, v, yy, dd); yv[u].z = yy; dxv[u].z = dd; }
+        if (p0 + 3 >= v.begin && p0 + 3 < v.end) { bwd_point<MAXC, WY, WDX>(xv[u].w, gv[u].w, v, yy, dd); yv[u].w = yy; dxv[u].w = dd; }
+        if (v.end > pl || qq + 1 >= r1) break;
+        v = run_view<true>(runs, ++qq, lds);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = ib + tid + u * bs;
+    if (!GUARD || i < vend) {
+      if (WY) __builtin_nontemporal_store(yv[u], y4 + i);
+      if (WDX) __builtin_nontemporal_store(dxv[u], dx4 + i);
+    }
+  }
+}
+
+template <int U, int MAXC, bool WY, bool WDX>
+__device__ __forceinline__ void slice_bwd(const BatchRun* __restrict__ runs, int r0, int r1, float4* lds,
+                                          const float* __restrict__ x, const float* __restrict__ g,
+                                          float* __restrict__ y, float* __restrict__ dx, bool vec, int wave0) {
+  const int64_t b = runs[r0].begin, e = runs[r1 - 1].end;
+  const Split sp = split_range(x, b, e, vec);
+  if (sp.vend <= sp.vbeg) {
+    slice_bwd_scalar<MAXC, WY, WDX>(runs, r0, r1, lds, x, g, y, dx, b, e);
+    return;
+  }
+  const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
+  const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x - phase);
+  const v4f* __restrict__ g4 = reinterpret_cast<const v4f*>(g - phase);
+  v4f* __restrict__ y4 = WY ? reinterpret_cast<v4f*>(y - phase) : nullptr;
+  v4f* __restrict__ dx4 = WDX ? reinterpret_cast<v4f*>(dx - phase) : nullptr;
+  const int tid = threadIdx.x;
+  const int64_t chunk = (int64_t)blockDim.x * U;
+  int q = r0;
+  RunView cur = run_view<true>(runs, q, lds);
+  int64_t ib = sp.vbeg;
+  for (; ib + chunk <= sp.vend; ib += chunk)
+    slice_bwd_iter<U, MAXC, false, WY, WDX>(runs, r1, lds, cur, q, x4, g4, y4, dx4, ib, sp.vend, phase, e, tid,
+                                            wave0);
+  if (ib < sp.vend)
+    slice_bwd_iter<U, MAXC, true, WY, WDX>(runs, r1, lds, cur, q, x4, g4, y4, dx4, ib, sp.vend, phase, e, tid,
+                                           wave0);
+  slice_bwd_scalar<MAXC, WY, WDX>(runs, r0, r1, lds, x, g, y, dx, b, sp.head);
+  const int64_t tail = 4 * sp.vend - phase;
+  slice_bwd_scalar<MAXC, WY, WDX>(runs, r0, r1, lds, x, g, y, dx, tail > sp.head ? tail : sp.head, e);
+}
+
+// As k_batch_fwd, with the slice's FP64 dL/dv regions (one per table, after
+// the images) zeroed before the first barrier; after the slice, one more
+// barrier and every region is stored, rounded to FP32, as its run's partial
+// sums (k_batch_dv_reduce adds them up).
 template <int U, bool WY, bool WDX>
 __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__ runs,
-                                                    const BatchGroup* __restrict__ groups,
+                                                    const BatchGroup* __restrict__ groups, int ngroups,
                                                     const float4* __restrict__ arena,
                                                     const float* __restrict__ x, const float* __restrict__ g,
                                                     float* __restrict__ y, float* __restrict__ dx,
-                                                    float* __restrict__ dv, int vec) {
+                                                    float* __restrict__ part, int vec) {
   extern __shared__ float4 lds_f4[];
-  const BatchGroup gp = groups[blockIdx.x];
-  if (gp.r0 >= gp.r1) return;
-  stage_words(arena + gp.img, gp.nwords, lds_f4);
-  double* dvz = reinterpret_cast<double*>(lds_f4 + gp.dv_lds);
-  for (int k = threadIdx.x; k < 2 * gp.dv_words; k += blockDim.x) dvz[k] = 0.0;
-  __syncthreads();
-  for (int q = gp.r0; q < gp.r1; ++q) {
-    const BatchRun r = runs[q];
-    Smem s = carve(lds_f4 + r.img_lds, r.N, r.K, false);
-    s.dv = reinterpret_cast<double*>(lds_f4 + r.dv_lds);
-    batch_bwd_run<U, WY, WDX>(r, s, x, g, y, dx, vec != 0);
-  }
-  __syncthreads();
-  for (int q = gp.r0; q < gp.r1; ++q) {
-    const BatchRun r = runs[q];
-    const double* d = reinterpret_cast<const double*>(lds_f4 + r.dv_lds);
-    float* out = dv + r.dv_off;
-    for (int k = threadIdx.x; k <= r.N; k += blockDim.x) {
-      const float v = (float)d[k];
-      if (v != 0.0f) unsafeAtomicAdd(out + k, v);
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
+  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+    const BatchGroup gp = groups[gi];
+    if (gi != (int)blockIdx.x) lds_barrier();
+    stage_words(arena + gp.img, gp.nwords, lds_f4);
+    double* dvz = reinterpret_cast<double*>(lds_f4 + gp.dv_lds);
+    for (int k = threadIdx.x; k < 2 * gp.dv_words; k += blockDim.x) dvz[k] = 0.0;
+    lds_barrier();
+    switch (gp.maxc) {
+      case 0:
+      case 1: slice_bwd<U, 1, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
+      case 2: slice_bwd<U, 2, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
+      case 3: slice_bwd<U, 3, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
+      case 4: slice_bwd<U, 4, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
+      default: slice_bwd<U, 0, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
     }
+    lds_barrier();
+    for (int q = gp.r0; q < gp.r1; ++q) {
+      const BatchRun r = runs[q];
+      const double* d = reinterpret_cast<const double*>(lds_f4 + r.dv_lds);
+      float* out = part + r.part;
+      for (int k = threadIdx.x; k <= r.N; k += blockDim.x) out[k] = (float)d[k];
+    }
+  }
+}
+
+// dL/dv of table blockIdx.x, entries 256 blockIdx.y + threadIdx.x: each the
+// sum, in FP64 and in slice order (a fixed order: the result does not depend
+// on how the workgroups ran), of its runs' partial sums; zero for a table
+// without points.  Writes every entry of dv.
+__global__ __launch_bounds__(256) void k_batch_dv_reduce(const float* __restrict__ part,
+                                                         const int64_t* __restrict__ tab_part,
+                                                         const int32_t* __restrict__ tab_first,
+                                                         const int64_t* __restrict__ tab_dv,
+                                                         float* __restrict__ dv) {
+  const int t = blockIdx.x;
+  const int64_t d0 = tab_dv[t], n1 = tab_dv[t + 1] - d0;
+  const int j0 = tab_first[t], j1 = tab_first[t + 1];
+  const int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (k < n1) {
+    double acc = 0.0;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {   // eight loads in flight, added in order
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[tab_part[j + q] + k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += (double)v[q];
+    }
+    for (; j < j1; ++j) acc += (double)part[tab_part[j] + k];
+    dv[d0 + k] = (float)acc;
   }
 }
 
@@ -283,12 +412,6 @@ __global__ __launch_bounds__(256) void k_batch_pack(const BatchTable* __restrict
   const EvalTable& t = bt.t;
   stage_table(t, nullptr, carve(bt.img, t.N, t.K, false));   // the same words a kernel stages
   if (threadIdx.x == 0) maxc[blockIdx.x] = (int32_t)t.meta[1];
-}
-
-__global__ void k_batch_zero(float* __restrict__ p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0f;
 }
 
 inline bool same_phase(const void* a, const void* b) {
@@ -308,8 +431,8 @@ hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchCo
   }
   const int key = (y != nullptr ? 2 : 0) | (dx != nullptr ? 1 : 0);
 #define PWL_BB(UU, A, B)                                                                              \
-  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, p.runs, p.groups, p.arena, x, g, \
-                     y, dx, dv, v)
+  hipLaunchKernelGGL((k_batch_bwd<UU, A, B>), grid, block, p.lds, s, p.runs, p.groups, p.ngroups, p.arena, x, g, \
+                     y, dx, bl.part, v)
 #define PWL_BB_U(UU)                             \
   switch (key) {                                 \
     case 0: PWL_BB(UU, false, false); break;     \
@@ -336,12 +459,10 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
   const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
                    (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const int v = vec ? 1 : 0;
-  if (backward) {
-    const int64_t zgrid = std::min<int64_t>(1024, (bl.dv_len + 255) / 256);
-    hipLaunchKernelGGL(k_batch_zero, dim3((unsigned)std::max<int64_t>(1, zgrid)), dim3(256), 0, s, dv, bl.dv_len);
-  }
   const hipError_t e = launch_plan(bl, backward ? bl.bwd : bl.fwd, c, x, g, y, dx, dv, v, s);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !backward) return e;
+  hipLaunchKernelGGL(k_batch_dv_reduce, dim3((unsigned)bl.T, (unsigned)((bl.max_n + 256) / 256)), dim3(256), 0, s,
+                     bl.part, bl.tab_part, bl.tab_first, bl.tab_dv, dv);
   return hipGetLastError();
 }
 

@@ -196,11 +196,11 @@ inline bool same_phase(const void* a, const void* b) {
 // two vectors per thread (the dL/dv LDS atomics favour a smaller register
 // footprint) in one 768-thread workgroup per CU - every further workgroup
 // there adds a dL/dv flush and a column to reduce, and larger grids measure
-// slower.  The batched kernels take 1024-thread workgroups: forward four
-// vectors per thread in a persistent grid of 3 per CU (1, 2, 4 and 8
-// measured 0.2-2% slower), fused backward one vector per thread and 16 per
-// CU.  pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 24}, {2, 768, 1}, {4, 1024, 3}, {1, 1024, 16}};
+// slower.  The batched kernels take 1024-thread workgroups in a persistent
+// grid of 3 per CU (1, 2, 4 and 8 measured 0.2-2% slower): forward four
+// vectors per thread, fused backward two (one measured 13% slower, four
+// spills).  pwl_set_launch overrides them.
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 24}, {2, 768, 1}, {4, 1024, 3}, {2, 1024, 3}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 int g_records = PWL_RECORDS_PACKED;

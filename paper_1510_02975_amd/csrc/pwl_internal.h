@@ -149,7 +149,7 @@ struct BatchRun {
   int32_t img_lds;           // the table's image: 16-byte word offset in the workgroup's LDS
   int32_t dv_lds;            // backward: word offset of the table's FP64 dL/dv in LDS
   int64_t begin, end;
-  int64_t dv_off;            // first of the table's N + 1 entries in the concatenated dL/dv
+  int64_t part;              // backward: first of the run's N + 1 partial dL/dv sums in the batch's buffer
   int32_t table, nvec, N, K;
   float a32, b32, scale32;
   int32_t maxc;              // most knots sharing one map cell (the unrolled compare depth)
@@ -190,6 +190,12 @@ struct BatchPlan {           // the work units of one launch
 struct BatchLaunch {
   BatchPlan fwd, bwd;
   int64_t dv_len;            // sum over tables of N + 1
+  int32_t T;
+  int32_t max_n;             // the largest table's N
+  float* part;               // device: every backward run's N + 1 partial dL/dv sums
+  const int64_t* tab_part;   // device: per table, in table order, its runs' offsets into part in slice order
+  const int32_t* tab_first;  // device [T + 1]: table t's entries of tab_part are [tab_first[t], tab_first[t+1])
+  const int64_t* tab_dv;     // device [T + 1]: table t's gradients are dv[tab_dv[t] .. tab_dv[t+1])
 };
 
 hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, float* y, float* dx,
