@@ -745,7 +745,7 @@ struct ClassPlan {
 // tables need more than `cap` bytes of LDS together - their images, a
 // contiguous span of the arena, and (backward) one FP64 dL/dv region per
 // table after them - becomes several groups, split at a table.  The kernels
-// deal the groups to their workgroups round-robin.
+// deal the groups to their workgroups round-robin, in the order below.
 ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>& img_word,
                       const std::vector<int32_t>& nvec, const std::vector<int32_t>& Ns, bool backward,
                       int64_t slice, size_t cap) {
@@ -797,6 +797,19 @@ ClassPlan plan_slices(const int64_t* offsets, int T, const std::vector<int64_t>&
     }
     close(q, img0, dv_words);
   }
+  // Deal each run of 8 consecutive units to one XCD: launch position
+  // 64 c + 8 j + i takes unit 64 c + 8 i + j (workgroups go to the XCDs
+  // round-robin, so position p runs on XCD p mod 8), keeping every block of
+  // 64 positions a window of 64 consecutive units.  A table's consecutive
+  // slices then read its image through one L2: the 4096-table forward
+  // measured 382.5 -> 375.8 us, the fused backward unchanged.
+  const int G = (int)p.groups.size(), full = G / 64 * 64;
+  std::vector<pwl::BatchGroup> order(p.groups);
+  for (int pos = 0; pos < full; ++pos) {
+    const int c = pos / 64, j = (pos / 8) % 8, i = pos % 8;
+    order[pos] = p.groups[64 * c + 8 * i + j];
+  }
+  p.groups.swap(order);
   return p;
 }
 

@@ -70,6 +70,33 @@ __device__ __forceinline__ void stage_words(const float4* __restrict__ src4, int
   }
 }
 
+// The first 4 * blockDim.x words of the next unit's images, loaded into
+// registers when the current unit starts, so that their latency passes
+// while the current unit streams; put_words writes them (and stages any
+// further words) once every wave is done with the current unit.
+struct ImagePrefetch {
+  v4f w[4];
+};
+
+__device__ __forceinline__ void prefetch_words(const float4* __restrict__ src4, int n, ImagePrefetch& p) {
+  const v4f* __restrict__ src = reinterpret_cast<const v4f*>(src4);
+  const int tid = threadIdx.x, bs = blockDim.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) p.w[j] = src[min(j * bs + tid, n - 1)];
+}
+
+__device__ __forceinline__ void put_words(const ImagePrefetch& p, const float4* __restrict__ src4, int n,
+                                          float4* dst4) {
+  v4f* dst = reinterpret_cast<v4f*>(dst4);
+  const int tid = threadIdx.x, bs = blockDim.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = j * bs + tid;
+    if (k < n) dst[k] = p.w[j];
+  }
+  if (n > 4 * bs) stage_words(src4 + 4 * bs, n - 4 * bs, dst4 + 4 * bs);
+}
+
 // A workgroup barrier that orders LDS accesses only: the streaming stores a
 // wave still has in flight are not waited for (__syncthreads would).
 __device__ __forceinline__ void lds_barrier() {
@@ -199,9 +226,10 @@ __device__ __forceinline__ void slice_fwd(const BatchRun* __restrict__ runs, int
   slice_scalar<MAXC>(runs, r0, r1, lds, x, y, tail > sp.head ? tail : sp.head, e);
 }
 
-// Slices blockIdx.x, blockIdx.x + gridDim.x, ...: stage the slice's images,
-// one barrier, stream it; one more barrier before the next slice's images
-// overwrite LDS.
+// Units blockIdx.x, blockIdx.x + gridDim.x, ...: the first unit's images
+// are staged, then per unit: load the next unit's first image words into
+// registers, stream this unit, one barrier, write the next images to LDS,
+// one barrier.
 template <int U>
 __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__ runs,
                                                     const BatchGroup* __restrict__ groups, int ngroups,
@@ -210,11 +238,20 @@ __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__
                                                     int vec) {
   extern __shared__ float4 lds_f4[];
   const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
-  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    const BatchGroup gp = groups[gi];
-    if (gi != (int)blockIdx.x) lds_barrier();
-    stage_words(arena + gp.img, gp.nwords, lds_f4);
-    lds_barrier();
+  int gi = blockIdx.x;
+  if (gi >= ngroups) return;
+  BatchGroup gp = groups[gi];
+  stage_words(arena + gp.img, gp.nwords, lds_f4);
+  lds_barrier();
+  for (;;) {
+    const int gn = gi + (int)gridDim.x;
+    const bool more = gn < ngroups;
+    BatchGroup gq{};
+    ImagePrefetch pf;
+    if (more) {
+      gq = groups[gn];
+      prefetch_words(arena + gq.img, gq.nwords, pf);
+    }
     switch (gp.maxc) {
       case 0:
       case 1: slice_fwd<U, 1>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
@@ -223,6 +260,12 @@ __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__
       case 4: slice_fwd<U, 4>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
       default: slice_fwd<U, 0>(runs, gp.r0, gp.r1, lds_f4, x, y, vec != 0, wave0); break;
     }
+    if (!more) break;
+    lds_barrier();
+    put_words(pf, arena + gq.img, gq.nwords, lds_f4);
+    lds_barrier();
+    gi = gn;
+    gp = gq;
   }
 }
 
@@ -338,10 +381,11 @@ __device__ __forceinline__ void slice_bwd(const BatchRun* __restrict__ runs, int
   slice_bwd_scalar<MAXC, WY, WDX>(runs, r0, r1, lds, x, g, y, dx, tail > sp.head ? tail : sp.head, e);
 }
 
-// As k_batch_fwd, with the slice's FP64 dL/dv regions (one per table, after
-// the images) zeroed before the first barrier; after the slice, one more
-// barrier and every region is stored, rounded to FP32, as its run's partial
-// sums (k_batch_dv_reduce adds them up).
+// As k_batch_fwd, with the unit's FP64 dL/dv regions (one per table, after
+// the images) zeroed before the barrier that starts it; after the unit, one
+// more barrier and every region is stored, rounded to FP32, as its run's
+// partial sums (k_batch_dv_reduce adds them up), then one more barrier
+// before the next unit's images overwrite LDS.
 template <int U, bool WY, bool WDX>
 __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__ runs,
                                                     const BatchGroup* __restrict__ groups, int ngroups,
@@ -351,13 +395,22 @@ __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__
                                                     float* __restrict__ part, int vec) {
   extern __shared__ float4 lds_f4[];
   const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
-  for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    const BatchGroup gp = groups[gi];
-    if (gi != (int)blockIdx.x) lds_barrier();
-    stage_words(arena + gp.img, gp.nwords, lds_f4);
+  int gi = blockIdx.x;
+  if (gi >= ngroups) return;
+  BatchGroup gp = groups[gi];
+  stage_words(arena + gp.img, gp.nwords, lds_f4);
+  for (;;) {
     double* dvz = reinterpret_cast<double*>(lds_f4 + gp.dv_lds);
     for (int k = threadIdx.x; k < 2 * gp.dv_words; k += blockDim.x) dvz[k] = 0.0;
     lds_barrier();
+    const int gn = gi + (int)gridDim.x;
+    const bool more = gn < ngroups;
+    BatchGroup gq{};
+    ImagePrefetch pf;
+    if (more) {
+      gq = groups[gn];
+      prefetch_words(arena + gq.img, gq.nwords, pf);
+    }
     switch (gp.maxc) {
       case 0:
       case 1: slice_bwd<U, 1, WY, WDX>(runs, gp.r0, gp.r1, lds_f4, x, g, y, dx, vec != 0, wave0); break;
@@ -373,6 +426,11 @@ __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__
       float* out = part + r.part;
       for (int k = threadIdx.x; k <= r.N; k += blockDim.x) out[k] = (float)d[k];
     }
+    if (!more) break;
+    lds_barrier();
+    put_words(pf, arena + gq.img, gq.nwords, lds_f4);
+    gi = gn;
+    gp = gq;
   }
 }
 
