@@ -70,31 +70,34 @@ __device__ __forceinline__ void stage_words(const float4* __restrict__ src4, int
   }
 }
 
-// The first 4 * blockDim.x words of the next unit's images, loaded into
+// The first W * blockDim.x words of the next unit's images, loaded into
 // registers when the current unit starts, so that their latency passes
 // while the current unit streams; put_words writes them (and stages any
 // further words) once every wave is done with the current unit.
+template <int W>
 struct ImagePrefetch {
-  v4f w[4];
+  v4f w[W];
 };
 
-__device__ __forceinline__ void prefetch_words(const float4* __restrict__ src4, int n, ImagePrefetch& p) {
+template <int W>
+__device__ __forceinline__ void prefetch_words(const float4* __restrict__ src4, int n, ImagePrefetch<W>& p) {
   const v4f* __restrict__ src = reinterpret_cast<const v4f*>(src4);
   const int tid = threadIdx.x, bs = blockDim.x;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) p.w[j] = src[min(j * bs + tid, n - 1)];
+  for (int j = 0; j < W; ++j) p.w[j] = src[min(j * bs + tid, n - 1)];
 }
 
-__device__ __forceinline__ void put_words(const ImagePrefetch& p, const float4* __restrict__ src4, int n,
+template <int W>
+__device__ __forceinline__ void put_words(const ImagePrefetch<W>& p, const float4* __restrict__ src4, int n,
                                           float4* dst4) {
   v4f* dst = reinterpret_cast<v4f*>(dst4);
   const int tid = threadIdx.x, bs = blockDim.x;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < W; ++j) {
     const int k = j * bs + tid;
     if (k < n) dst[k] = p.w[j];
   }
-  if (n > 4 * bs) stage_words(src4 + 4 * bs, n - 4 * bs, dst4 + 4 * bs);
+  if (n > W * bs) stage_words(src4 + W * bs, n - W * bs, dst4 + W * bs);
 }
 
 // A workgroup barrier that orders LDS accesses only: the streaming stores a
@@ -119,7 +122,10 @@ __device__ __forceinline__ RunView run_view(const BatchRun* __restrict__ runs, i
   RunView v;
   v.t = run_table(r);
   v.s = carve(lds + r.img_lds, r.N, r.K, false);
-  if (DV) v.s.dv = reinterpret_cast<double*>(lds + r.dv_lds);
+  if (DV) {
+    v.s.dv = reinterpret_cast<double*>(lds + r.dv_lds);
+    v.s.dvc = dv_copies(r.N);
+  }
   v.begin = r.begin;
   v.end = r.end;
   return v;
@@ -227,9 +233,9 @@ __device__ __forceinline__ void slice_fwd(const BatchRun* __restrict__ runs, int
 }
 
 // Units blockIdx.x, blockIdx.x + gridDim.x, ...: the first unit's images
-// are staged, then per unit: load the next unit's first image words into
-// registers, stream this unit, one barrier, write the next images to LDS,
-// one barrier.
+// are staged, then per unit: load the next unit's first image words (four
+// per thread) into registers, stream this unit, one barrier, write the next
+// images to LDS, one barrier.
 template <int U>
 __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__ runs,
                                                     const BatchGroup* __restrict__ groups, int ngroups,
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(1024) void k_batch_fwd(const BatchRun* __restrict__
     const int gn = gi + (int)gridDim.x;
     const bool more = gn < ngroups;
     BatchGroup gq{};
-    ImagePrefetch pf;
+    ImagePrefetch<4> pf;
     if (more) {
       gq = groups[gn];
       prefetch_words(arena + gq.img, gq.nwords, pf);
@@ -385,7 +391,8 @@ __device__ __forceinline__ void slice_bwd(const BatchRun* __restrict__ runs, int
 // the images) zeroed before the barrier that starts it; after the unit, one
 // more barrier and every region is stored, rounded to FP32, as its run's
 // partial sums (k_batch_dv_reduce adds them up), then one more barrier
-// before the next unit's images overwrite LDS.
+// before the next unit's images overwrite LDS.  Two image words per thread
+// are prefetched (four would spill: the backward holds twice the data).
 template <int U, bool WY, bool WDX>
 __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__ runs,
                                                     const BatchGroup* __restrict__ groups, int ngroups,
@@ -406,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__
     const int gn = gi + (int)gridDim.x;
     const bool more = gn < ngroups;
     BatchGroup gq{};
-    ImagePrefetch pf;
+    ImagePrefetch<2> pf;
     if (more) {
       gq = groups[gn];
       prefetch_words(arena + gq.img, gq.nwords, pf);
@@ -423,8 +430,13 @@ __global__ __launch_bounds__(1024) void k_batch_bwd(const BatchRun* __restrict__
     for (int q = gp.r0; q < gp.r1; ++q) {
       const BatchRun r = runs[q];
       const double* d = reinterpret_cast<const double*>(lds_f4 + r.dv_lds);
+      const int c = dv_copies(r.N);
       float* out = part + r.part;
-      for (int k = threadIdx.x; k <= r.N; k += blockDim.x) out[k] = (float)d[k];
+      for (int k = threadIdx.x; k <= r.N; k += blockDim.x) {
+        double acc = d[k * c];
+        for (int j = 1; j < c; ++j) acc += d[k * c + j];   // copies in a fixed order
+        out[k] = (float)acc;
+      }
     }
     if (!more) break;
     lds_barrier();

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __r
   const Smem s = carve(lds_f4, t.N, t.K, WDV);
   stage_table(t, vo, s);
   if (WDV)
-    for (int k = threadIdx.x; k <= t.N; k += blockDim.x) s.dv[k] = 0.0;
+    for (int k = threadIdx.x; k < (t.N + 1) * s.dvc; k += blockDim.x) s.dv[k] = 0.0;
   __syncthreads();
   using B = Bwd<U, WY, WDX, WDV>;
   const int64_t blk = blockIdx.x, nblk = gridDim.x;
@@ -104,7 +104,11 @@ __global__ __launch_bounds__(1024) void k_eval_bwd(EvalTable t, const float* __r
     __syncthreads();
     const int G = gridDim.x, b = blockIdx.x;
     const int col = (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
-    for (int k = threadIdx.x; k <= t.N; k += blockDim.x) part[(int64_t)k * G + col] = (float)s.dv[k];
+    for (int k = threadIdx.x; k <= t.N; k += blockDim.x) {
+      double acc = s.dv[k * s.dvc];
+      for (int j = 1; j < s.dvc; ++j) acc += s.dv[k * s.dvc + j];   // the copies, in a fixed order
+      part[(int64_t)k * G + col] = (float)acc;
+    }
   }
 }
 

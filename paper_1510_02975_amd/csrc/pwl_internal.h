@@ -82,11 +82,20 @@ __host__ __device__ inline int image_words_soa(int N, int K) {
   return 4 * image_soa_field_words(N) + image_knot_words(N) + image_map_words(K);
 }
 
+// Copies of a workgroup's FP64 dL/dv in LDS (backward kernels): lane l adds
+// into copy l mod copies.  With few entries the 64 lanes of a wave would
+// otherwise often add into the same entry, and same-address LDS atomics of
+// one instruction serialise; the copies are summed, in order, at the flush.
+__host__ __device__ inline int dv_copies(int N) {
+  const int m = N + 1;
+  return m <= 32 ? 8 : (m <= 64 ? 4 : (m <= 128 ? 2 : 1));
+}
+
 // LDS bytes of the evaluation kernels for a table of N segments and K cells:
 // the image, then (backward) the workgroup's FP64 dL/dv.
 inline size_t eval_lds_bytes(int N, int K, bool backward) {
   size_t b = 16 * (size_t)image_words(N, K);
-  if (backward) b += sizeof(double) * (size_t)(N + 1);
+  if (backward) b += sizeof(double) * (size_t)(N + 1) * (size_t)dv_copies(N);
   return b;
 }
 
@@ -171,7 +180,7 @@ static_assert(sizeof(BatchGroup) == 32, "BatchGroup is 32 bytes");
 
 // LDS of one table in a batched workgroup: its image and (backward) its FP64
 // dL/dv, in 16-byte words.
-inline int batch_dv_words(int N) { return ((N + 1) * (int)sizeof(double) + 15) / 16; }
+inline int batch_dv_words(int N) { return ((N + 1) * dv_copies(N) * (int)sizeof(double) + 15) / 16; }
 inline size_t batch_table_lds_bytes(int N, int K, bool backward) {
   return 16 * ((size_t)image_words(N, K) + (backward ? (size_t)batch_dv_words(N) : 0));
 }

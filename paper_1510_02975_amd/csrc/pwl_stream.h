@@ -20,7 +20,8 @@ struct Smem {
   float4* rec;      // [N]           {x_k, v_k, slope_k, x_{k+1}}
   float* knot;      // [N + pad]     knot[k] = x_k for 1 <= k <= N-1, NaN elsewhere
   uint16_t* lo;     // [K + 1]       lo[u] = #{interior knots in cells < u}; lo[K] = N - 1
-  double* dv;       // [N + 1]       backward only: this workgroup's dL/dv
+  double* dv;       // [(N + 1) dvc] backward only: this workgroup's dL/dv, entry k of copy c at k dvc + c
+  int dvc;          //               copies of dL/dv (a power of two; lane l adds into copy l mod dvc)
   __device__ __forceinline__ float4 record(int k) const { return rec[k]; }
   __device__ __forceinline__ void put_record(int k, float4 r) const { rec[k] = r; }
 };
@@ -65,6 +66,7 @@ __device__ __forceinline__ Smem carve(void* base, int N, int K, bool backward) {
   s.knot = reinterpret_cast<float*>(s.rec + N);
   s.lo = reinterpret_cast<uint16_t*>(reinterpret_cast<float4*>(s.knot) + image_knot_words(N));
   s.dv = backward ? reinterpret_cast<double*>(reinterpret_cast<float4*>(s.lo) + image_map_words(K)) : nullptr;
+  s.dvc = backward ? dv_copies(N) : 1;
   return s;
 }
 
@@ -316,8 +318,9 @@ __device__ __forceinline__ void backward_point(float x, float g, const EvalTable
       const float rh = __builtin_amdgcn_rcpf(r.w - r.x);   // 1/h, within 1 ulp
       const float w0 = ((r.w - xc) * rh) * g;   // (1 - delta) g
       const float w1 = (d * rh) * g;            // delta g
-      __hip_atomic_fetch_add(s.dv + seg, (double)w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(s.dv + seg + 1, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const int at = seg * s.dvc + ((int)__lane_id() & (s.dvc - 1));
+      __hip_atomic_fetch_add(s.dv + at, (double)w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(s.dv + at + s.dvc, (double)w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
