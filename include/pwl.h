@@ -316,9 +316,11 @@ pwl_status pwl_batch_eval(pwl_batch* bt, const float* x, float* y, void* stream)
  * dx (each nullable) as in pwl_eval_backward; g is required unless the
  * batch has no points; dv (required) is the concatenation of every table's
  * N_t + 1 gradients, table t first, and is OVERWRITTEN (zero for tables
- * without points).  dv is summed in a fixed order, so repeated calls give
- * the same bits.  The partial sums live in the batch: calls on one batch
- * must not overlap (on different streams, or with a replay of its graph).
+ * without points).  The slices' partial sums are added in a fixed order,
+ * so dv does not depend on the order in which workgroups ran (within a
+ * slice the FP64 LDS sums depend on it only in their last FP64 bits).  The
+ * partial sums live in the batch: calls on one batch must not overlap (on
+ * different streams, or with a replay of its graph).
  */
 pwl_status pwl_batch_eval_backward(pwl_batch* bt, const float* x, const float* g, float* y, float* dx,
                                    float* dv, void* stream);
