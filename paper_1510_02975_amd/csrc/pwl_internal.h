@@ -87,8 +87,8 @@ __host__ __device__ inline int image_words_soa(int N, int K) {
 // otherwise often add into the same entry, and same-address LDS atomics of
 // one instruction serialise; the copies are summed, in order, at the flush.
 __host__ __device__ inline int dv_copies(int N) {
-  const int m = N + 1;
-  return m <= 32 ? 8 : (m <= 64 ? 4 : (m <= 128 ? 2 : 1));
+  const int m = N + 1;   // at most 1024 doubles (8 KB) in all
+  return m <= 64 ? 16 : (m <= 128 ? 8 : (m <= 256 ? 4 : (m <= 512 ? 2 : 1)));
 }
 
 // LDS bytes of the evaluation kernels for a table of N segments and K cells:

@@ -24,10 +24,11 @@ CASES = [
     (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 4096, O.OPTIMAL, O.PROJ),
     (O.BESSEL_J0, (1.0,), 0.0, 50.0, 1024, O.OPTIMAL, O.INTERP),
     (O.GAUSSIAN, (1.0, 1.0), -2.0, 2.0, 1, O.UNIFORM, O.PROJ),
-    # few dL/dv entries: kept in 8, 4 and 2 LDS copies
+    # few dL/dv entries: kept in 16, 8, 4 and 2 LDS copies
     (O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 16, O.OPTIMAL, O.PROJ),
-    (O.BESSEL_J0, (1.0,), 0.0, 50.0, 40, O.UNIFORM, O.INTERP),
-    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 100, O.OPTIMAL, O.PROJ),
+    (O.BESSEL_J0, (1.0,), 0.0, 50.0, 100, O.UNIFORM, O.INTERP),
+    (O.LORENTZIAN, (1.0, 1.0), -20.0, 20.0, 200, O.OPTIMAL, O.PROJ),
+    (O.GAUSSIAN, (1.0, 1.0), -4.0, 4.0, 400, O.UNIFORM, O.PROJ),
 ]
 
 

@@ -36,7 +36,7 @@ def test_noalloc_backward_matches_backward_twice():
     import oracle as O
     import paper_1510_02975_amd as P
     library()
-    # second call: smaller input, another table (N = 24: its dL/dv in 8 LDS copies)
+    # second call: smaller input, another table (N = 24: its dL/dv in 16 LDS copies)
     cases = [(1024, (1 << 22) + 3, 1.5), (24, 4099, 1.0)]
     for N, n, sigma in cases:
         say("noalloc backward: Gaussian optimal N=%d projection, n=%d" % (N, n))
