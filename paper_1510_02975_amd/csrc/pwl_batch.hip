@@ -489,7 +489,7 @@ inline bool same_phase(const void* a, const void* b) {
 }
 
 hipError_t launch_plan(const BatchLaunch& bl, const BatchPlan& p, const LaunchConfig& c, const float* x,
-                       const float* g, float* y, float* dx, float* dv, int v, hipStream_t s) {
+                       const float* g, float* y, float* dx, int v, hipStream_t s) {
   const dim3 grid(p.grid), block(c.block);
   if (g == nullptr) {
     switch (c.unroll) {
@@ -529,7 +529,7 @@ hipError_t launch_batch(const BatchLaunch& bl, const float* x, const float* g, f
   const bool vec = same_phase(x, y) && same_phase(x, g) && same_phase(x, dx) &&
                    (reinterpret_cast<uintptr_t>(x) & 3u) == 0;
   const int v = vec ? 1 : 0;
-  const hipError_t e = launch_plan(bl, backward ? bl.bwd : bl.fwd, c, x, g, y, dx, dv, v, s);
+  const hipError_t e = launch_plan(bl, backward ? bl.bwd : bl.fwd, c, x, g, y, dx, v, s);
   if (e != hipSuccess || !backward) return e;
   hipLaunchKernelGGL(k_batch_dv_reduce, dim3((unsigned)bl.T, (unsigned)((bl.max_n + 256) / 256)), dim3(256), 0, s,
                      bl.part, bl.tab_part, bl.tab_first, bl.tab_dv, dv);

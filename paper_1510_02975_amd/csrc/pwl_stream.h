@@ -405,58 +405,6 @@ __device__ __forceinline__ void fwd_range(const EvalTable& t, const S& s, const 
     y[i] = eval_point<MAXC>(x[i], t, s);
 }
 
-// Forward over points [begin, end) by this workgroup alone (a batch run).
-// Runs are short (a workgroup walks many), so the scalar head and tail and
-// the partial last vector iteration are loaded before the full iterations
-// stream and finished after them: their memory latency overlaps the stream
-// instead of adding a serial wait to every run.
-template <int U, int MAXC>
-__device__ __forceinline__ void fwd_run(const EvalTable& t, const Smem& s, const float* __restrict__ x,
-                                        float* __restrict__ y, int64_t begin, int64_t end, bool vec) {
-  const Split sp = split_range(x, begin, end, vec);
-  const int64_t bs = blockDim.x, tid = threadIdx.x;
-  const int64_t phase = (int64_t)((reinterpret_cast<uintptr_t>(x) >> 2) & 3);
-  const bool has_vec = sp.vend > sp.vbeg;
-  const int64_t tail0 = has_vec ? 4 * sp.vend - phase : sp.head;
-  const int64_t tail_start = tail0 > sp.head ? tail0 : sp.head;
-  // scalar points: at most 3 + 3 when vectorised, every point otherwise
-  if (!has_vec) {
-    for (int64_t i = begin + tid; i < end; i += bs) y[i] = eval_point<MAXC>(x[i], t, s);
-    return;
-  }
-  const int64_t ih = begin + tid, it = tail_start + tid;
-  const bool dh = ih < sp.head, dt = it < end;
-  const float xh = dh ? x[ih] : 0.0f;
-  const float xt = dt ? x[it] : 0.0f;
-  const v4f* __restrict__ x4 = reinterpret_cast<const v4f*>(x - phase);
-  v4f* __restrict__ y4 = reinterpret_cast<v4f*>(y - phase);
-  const int64_t chunk = bs * U;
-  const int64_t nfull = (sp.vend - sp.vbeg) / chunk;
-  const int64_t rbase = sp.vbeg + nfull * chunk + tid;   // this thread's vectors of the partial iteration
-  v4f xr[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = rbase + u * bs;
-    if (i < sp.vend) xr[u] = __builtin_nontemporal_load(x4 + i);
-  }
-  for (int64_t base = sp.vbeg + tid; base < sp.vbeg + nfull * chunk; base += chunk)
-    fwd_iter<U, MAXC, false>(t, s, x4, y4, base, bs, sp.vend);
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = rbase + u * bs;
-    if (i < sp.vend) {
-      v4f yv;
-      yv.x = eval_point<MAXC>(xr[u].x, t, s);
-      yv.y = eval_point<MAXC>(xr[u].y, t, s);
-      yv.z = eval_point<MAXC>(xr[u].z, t, s);
-      yv.w = eval_point<MAXC>(xr[u].w, t, s);
-      __builtin_nontemporal_store(yv, y4 + i);
-    }
-  }
-  if (dh) y[ih] = eval_point<MAXC>(xh, t, s);
-  if (dt) y[it] = eval_point<MAXC>(xt, t, s);
-}
-
 template <int U, bool WY, bool WDX, bool WDV>
 struct Bwd {
   template <int MAXC, bool GUARD>
