@@ -26,7 +26,7 @@ from .timing import timed_median, warm_up
 DEFAULT_CANDIDATES = {
     "unroll": (1, 2, 4),
     "block": (256, 512, 768, 1024),
-    "wg_per_cu": (1, 2, 4, 8, 16, 24, 32),
+    "wg_per_cu": (1, 2, 3, 4, 6, 8, 16, 24, 32),
 }
 LOCATE_NAMES = {B.LOCATE_MAP: "map", B.LOCATE_SEARCH: "search"}
 RECORDS_NAMES = {B.RECORDS_PACKED: "packed", B.RECORDS_SOA: "soa", B.RECORDS_PAIRS: "pairs"}

@@ -194,17 +194,18 @@ inline bool same_phase(const void* a, const void* b) {
 // of table it stages, but never below one workgroup per CU (nor above one
 // per iteration of work).  The defaults are the autotuner's choice on
 // MI355X: forward at 2^28 points, four vectors per thread in 1024-thread
-// workgroups, up to 24 per CU (at N = 1024 the staging rule leaves 18,
+// workgroups, up to 32 per CU (at N = 1024 the staging rule leaves 18,
 // which measured 333 us against 335 us for 16; at N = 4096 it leaves about
 // 3); fused backward at 2^26 points,
 // two vectors per thread (the dL/dv LDS atomics favour a smaller register
 // footprint) in one 768-thread workgroup per CU - every further workgroup
-// there adds a dL/dv flush and a column to reduce, and larger grids measure
-// slower.  The batched kernels take 1024-thread workgroups in a persistent
-// grid of 3 per CU (1, 2, 4 and 8 measured 0.2-2% slower): forward four
-// vectors per thread, fused backward two (one measured 13% slower, four
-// spills).  pwl_set_launch overrides them.
-constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 24}, {2, 768, 1}, {4, 1024, 3}, {2, 1024, 3}};
+// there adds a dL/dv flush and a column to reduce.  The batched kernels
+// take 1024-thread workgroups and four vectors per thread: the forward a
+// persistent grid of 3 per CU, the fused backward 32 per CU (about one
+// slice per workgroup, in rounds; its four-vector body spills a little and
+// still measured 3% faster than two vectors in 3 per CU).  pwl_set_launch
+// overrides them.
+constexpr LaunchConfig kDefaultLaunch[4] = {{4, 1024, 32}, {2, 768, 1}, {4, 1024, 3}, {4, 1024, 32}};
 LaunchConfig g_launch[4] = {kDefaultLaunch[0], kDefaultLaunch[1], kDefaultLaunch[2], kDefaultLaunch[3]};
 int g_locate = PWL_LOCATE_MAP;
 int g_records = PWL_RECORDS_PACKED;
