@@ -7,11 +7,14 @@
 // kernel's vector iterations (two by default) at fixed positions of the
 // concatenated arrays, whatever the tables, and lists per slice the
 // (table, begin, end) runs it covers; a slice whose tables' LDS images
-// would not fit is split at a table.  A grid of a few workgroups per CU
-// takes the slices round-robin (workgroup b: slices b, b + grid, ...), so
-// the workgroups in flight stream neighbouring slices and every slice is
+// would not fit is split at a table.  The grid's workgroups take the slices
+// round-robin (workgroup b: launch positions b, b + grid, ...; the host
+// orders the positions so that runs of 8 consecutive slices share an XCD),
+// so the workgroups in flight stream neighbouring slices and every slice is
 // streamed in full iterations: a slice boundary, not a table boundary, ends
-// an iteration.  Per slice a workgroup copies its tables' images (one
+// an iteration.  The forward's grid is persistent (a few workgroups per CU);
+// the backward's has about one workgroup per slice.  Per slice a workgroup
+// copies its tables' images (one
 // contiguous span of the batch's image arena) into LDS, passes a barrier and
 // streams the slice as one range; each wave looks up the run of its
 // 64 vectors (scalar: the slice's runs are in order) and, where the vectors
