@@ -295,10 +295,12 @@ pwl_status pwl_locate(const pwl_table* t, const float* x, int32_t* seg, int64_t 
  * iterations (unroll * block * 8 points) from point 0 on, whatever the
  * tables; a slice whose tables' LDS images do not fit together is split at
  * a table.  The grid holds wg_per_cu workgroups per CU (fewer if there are
- * fewer slices) and workgroup b takes slices b, b + grid, ...: per slice it
- * copies the images of the slice's tables into LDS and streams the slice as
- * one range, each wave with the table of its points.
- * Backward: the same, in slices of its own launch shape; per slice the
+ * fewer slices) and workgroup b takes the slices at launch positions b,
+ * b + grid, ... (runs of 8 consecutive slices are placed on one XCD): per
+ * slice it copies the images of the slice's tables into LDS and streams the
+ * slice as one range, each wave with the table of its points.
+ * Backward: the same, in slices of four of its own iterations
+ * (unroll * block * 16 points); per slice the
  * workgroup also sums every point's hat weights into one FP64 dL/dv region
  * per table in LDS and stores each region, rounded to FP32, as that run's
  * N + 1 partial sums in a buffer the batch owns; a second kernel adds each
