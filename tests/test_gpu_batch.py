@@ -165,6 +165,54 @@ def test_batch_misaligned_and_degenerate_shapes():
     bt.free()
 
 
+def _expected_runs(offs, slice_pts):
+    """Runs of the slice plan: one per (slice, table with points in it)."""
+    total = int(offs[-1])
+    runs = 0
+    for s0 in range(0, total, slice_pts):
+        s1 = min(total, s0 + slice_pts)
+        runs += int(np.count_nonzero((offs[:-1] < s1) & (offs[1:] > s0) & (offs[1:] > offs[:-1])))
+    return runs
+
+
+@pytest.mark.parametrize("shapes", [((4, 1024, 3), (4, 1024, 32)), ((2, 512, 2), (1, 256, 4))],
+                         ids=["tuned", "small"])
+def test_batch_plan_slices(shapes):
+    """The slice plan as the host builds it: slices of 2 (forward) and 4
+    (backward) vector iterations of the launch shape, one run per table per
+    slice it meets (empty tables none), no more workgroups than wg_per_cu
+    per CU; and the outputs of both directions equal the per-table kernels'."""
+    import paper_1510_02975_amd as P
+    library()
+    dev = device()
+    num_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    t1 = P.pwl_build(O.GAUSSIAN, (1.0, 1.0), -5.0, 5.0, 300, O.OPTIMAL, O.PROJ)
+    t2 = P.pwl_build(O.BESSEL_J0, (1.0,), 0.0, 50.0, 64, O.UNIFORM, O.INTERP)
+    counts = [100000, 0, 1, 70001, 3, 0, 250000, 17, 40000]
+    tabs = [t1 if k % 2 == 0 else t2 for k in range(len(counts))]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n = int(offs[-1])
+    x = torch.from_numpy(W.uniform_points(-6.0, 51.0, n, 13)).to(dev)
+    g = torch.from_numpy(W.upstream_grad(n, 14)).to(dev)
+    (uf, bf, wf), (ub, bb, wb) = shapes
+    with launch_shape(P, P.KERNEL_BATCH, shapes[0]), launch_shape(P, P.KERNEL_BATCH_BACKWARD, shapes[1]):
+        bt = P.pwl_batch_create(tabs, offs)
+        say("plan: grid fwd %d bwd %d, runs fwd %d bwd %d" % (bt.grid_fwd, bt.grid_bwd, bt.runs_fwd, bt.runs_bwd))
+        assert bt.runs_fwd == _expected_runs(offs, 2 * 4 * bf * uf)
+        assert bt.runs_bwd == _expected_runs(offs, 4 * 4 * bb * ub)
+        assert 1 <= bt.grid_fwd <= num_cu * wf and 1 <= bt.grid_bwd <= num_cu * wb
+        y = P.pwl_batch_eval(bt, x)
+        yb, dxb, _ = P.pwl_batch_eval_backward(bt, x, g)
+        for t, o0, o1 in zip(tabs, offs[:-1], offs[1:]):
+            if o1 > o0:
+                assert torch.equal(y[o0:o1], P.pwl_eval(t, x[o0:o1]))
+                y1, dx1, _ = P.pwl_eval_backward(t, x[o0:o1], g[o0:o1], want=("y", "dx"))
+                assert torch.equal(yb[o0:o1], y1) and torch.equal(dxb[o0:o1], dx1)
+        bt.free()
+    t1.free()
+    t2.free()
+
+
 @pytest.mark.parametrize("shape", [(4, 1024, 3), (1, 256, 1), (2, 512, 8)], ids=["u4", "u1-256", "u2-512"])
 def test_batch_forward_slices_cross_tables(shape):
     """The forward's slices against table boundaries: runs of 1 to 300
