@@ -269,7 +269,7 @@ pwl_status pwl_eval_backward_noalloc(const pwl_table* t, const float* v_override
 
 /*
  * pwl_locate - the 0-based segment index i with x_i <= x < x_{i+1} of each
- * point (step 1 of Algorithm 1), after clamping to [a, b]; x = b gives N-1,
+ * point (the segment locate of Algorithm 1), after clamping to [a, b]; x = b gives N-1,
  * NaN gives 0.  seg is device int32 [n].  It runs the very locate the
  * evaluation kernels run for this table (the same unrolled compare depth, or
  * the binary search when pwl_set_locate selected it), so the indices are
@@ -426,8 +426,8 @@ pwl_status pwl_get_launch(int32_t kernel, int32_t* unroll, int32_t* block, int32
 #define PWL_LOCATE_SEARCH 1   /* branch-free binary search over the knots in LDS (Sec. IV-V)  */
 
 /*
- * pwl_set_locate - process-wide segment locate of pwl_eval (step 1 of
- * Algorithm 1): the index map, or the paper's own GPU technique, a binary
+ * pwl_set_locate - process-wide segment locate of pwl_eval (the first
+ * part of Algorithm 1): the index map, or the paper's own GPU technique, a binary
  * search unrolled into selects, over the knots staged in LDS (no map).
  * Both give the same segment, so the outputs are bit-identical; the choice
  * is a speed A/B.  Takes effect for later launches.  pwl_get_locate reads

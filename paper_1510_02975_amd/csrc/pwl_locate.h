@@ -1,4 +1,4 @@
-// Segment locate (step 1 of Algorithm 1, Sec. IV) through a uniform index map.
+// Segment locate (the first part of Algorithm 1, Sec. IV) through a uniform index map.
 //
 // The paper locates x in a non-uniform partition with an O(log N) binary
 // search (Sec. IV) unrolled into selects (Sec. V).  Here the domain is cut

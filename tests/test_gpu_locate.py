@@ -1,7 +1,7 @@
 """The paper's own GPU locate - a branch-free binary search over the knots
 (Sec. IV-V), here over the knots staged in LDS - and the default index map,
 each against the FP64 oracle: both must return the oracle's segment index
-(Algorithm 1, step 1) on the GPU's own knots, exactly, and pwl_eval through
+(the segment locate of Algorithm 1) on the GPU's own knots, exactly, and pwl_eval through
 either must match the oracle's evaluation; the two modes' outputs are then
 bit-identical.  The same for the three arrangements of the per-segment
 data in LDS (packed records, structure of arrays, value/slope pairs;
