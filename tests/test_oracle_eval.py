@@ -5,7 +5,6 @@ partition of unity of the hat functions."""
 import math
 
 import numpy as np
-import pytest
 
 import oracle as O
 

@@ -5,7 +5,6 @@ function, exactness at the samples, and a table built from samples of the
 Gaussian against the one built from the Gaussian itself."""
 
 import numpy as np
-import pytest
 
 import oracle as O
 
