@@ -577,7 +577,7 @@ def main():
                     help="for profiler runs: the batch leg times only its batched launches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         return 2
 
